@@ -1,0 +1,121 @@
+"""Seeded synthetic inputs for the heterogeneous micromechanics RVE.
+
+The paper's benchmark (Sec. V-A) is a two-phase composite RVE whose meshes,
+microstructures and fields are not published; these generators stand in for
+them.  Every array is a pure function of its arguments and seed.  This module
+holds geometry and random-number recipes only: no finite-element arithmetic
+(no shape functions, stresses, assembly or solves), so the CPU oracle and the
+HIP path can both be fed from it without sharing any of the method.
+
+Conventions of the structured cube mesh on [0,1]^3 with n elements per side:
+  element (a,b,c) has id a + n*(b + n*c) and centroid ((a+.5)h, (b+.5)h, (c+.5)h)
+  node (i,j,k) has id i + (n+1)*(j + (n+1)*k); dof = 3*node + component.
+Phase ids: 0 = matrix, 1 = inclusion / fiber.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+MATRIX, INCLUSION = 0, 1
+
+
+def element_centroids(n: int) -> np.ndarray:
+    """(n^3, 3) centroids of the elements of the n^3 unit-cube mesh, element order."""
+    h = 1.0 / n
+    c1 = (np.arange(n) + 0.5) * h
+    cz, cy, cx = np.meshgrid(c1, c1, c1, indexing="ij")  # a (x) varies fastest
+    return np.stack([cx.ravel(), cy.ravel(), cz.ravel()], axis=1)
+
+
+def sphere_phase(n: int, radius: float = 0.3, center=(0.5, 0.5, 0.5)) -> np.ndarray:
+    """Centered spherical inclusion: phase 1 where |centroid - center| < radius (strict)."""
+    d = element_centroids(n) - np.asarray(center, dtype=np.float64)
+    return (np.einsum("ij,ij->i", d, d) < radius * radius).astype(np.uint8)
+
+
+def rsa_fiber_centers(n_fibers: int = 64, radius: float = 0.05, seed: int = 2,
+                      max_attempts: int = 10_000_000) -> np.ndarray:
+    """Periodic random sequential addition of non-overlapping disks in [0,1)^2.
+
+    Candidates are successive uniform pairs from numpy's default_rng(seed)
+    (PCG64); a candidate is kept when its minimum-image distance to every kept
+    center is at least 2*radius.  Raises if max_attempts candidates run out.
+    """
+    rng = np.random.default_rng(seed)
+    centers = np.empty((0, 2))
+    attempts, block = 0, 4096
+    min_d2 = (2.0 * radius) ** 2
+    while len(centers) < n_fibers:
+        cand = rng.random((block, 2))
+        for p in cand:
+            attempts += 1
+            if attempts > max_attempts:
+                raise RuntimeError("RSA did not place all fibers")
+            if len(centers):
+                d = centers - p
+                d -= np.round(d)  # minimum image on the unit torus
+                if np.min(np.einsum("ij,ij->i", d, d)) < min_d2:
+                    continue
+            centers = np.vstack([centers, p])
+            if len(centers) == n_fibers:
+                break
+    return centers
+
+
+def fiber_phase(n: int, n_fibers: int = 64, radius: float = 0.05, seed: int = 2) -> np.ndarray:
+    """z-aligned cylindrical fibers: phase 1 where the centroid's (x,y) lies strictly
+    within radius of a fiber center (minimum image)."""
+    centers = rsa_fiber_centers(n_fibers, radius, seed)
+    xy = element_centroids(n)[:, :2]
+    phase = np.zeros(len(xy), dtype=np.uint8)
+    for c in centers:
+        d = xy - c
+        d -= np.round(d)
+        phase |= (np.einsum("ij,ij->i", d, d) < radius * radius).astype(np.uint8)
+    return phase
+
+
+def lognormal_field(n: int, mean: float = 1.0, cov: float = 0.5, corr_len: float = 0.1,
+                    seed: int = 3) -> np.ndarray:
+    """Per-element log-normal field with separable exponential correlation.
+
+    g is a unit Gaussian field with covariance exp(-(|dx|+|dy|+|dz|)/corr_len) on
+    the element centroids, sampled exactly by a stationary AR(1) recursion along
+    each axis (g_0 = xi_0, g_k = rho g_{k-1} + sqrt(1-rho^2) xi_k, rho = exp(-h/corr_len)).
+    The field is mean * exp(m + s g) with s^2 = ln(1 + cov^2), m = -s^2/2.
+    """
+    h = 1.0 / n
+    rho = np.exp(-h / corr_len)
+    c = np.sqrt(1.0 - rho * rho)
+    g = np.random.default_rng(seed).standard_normal((n, n, n))  # [c][b][a]
+    for axis in (2, 1, 0):
+        g = np.moveaxis(g, axis, 0).copy()
+        for k in range(1, n):
+            g[k] = rho * g[k - 1] + c * g[k]
+        g = np.moveaxis(g, 0, axis)
+    s2 = np.log1p(cov * cov)
+    return mean * np.exp(-0.5 * s2 + np.sqrt(s2) * g.reshape(-1))
+
+
+def uniform_field(n_items: int, lo: float, hi: float, seed: int) -> np.ndarray:
+    """i.i.d. U(lo, hi) per item from default_rng(seed)."""
+    return np.random.default_rng(seed).uniform(lo, hi, n_items)
+
+
+def random_displacement(n: int, lo: float = -1e-3, hi: float = 1e-3, seed: int = 1) -> np.ndarray:
+    """U(lo, hi) on every dof of the n^3 mesh (interleaved dof = 3*node + c)."""
+    return np.random.default_rng(seed).uniform(lo, hi, 3 * (n + 1) ** 3)
+
+
+def boundary_dof_mask(n: int) -> np.ndarray:
+    """uint8 per dof: 1 for all three dofs of every node with an index in {0, n}."""
+    idx = np.arange(n + 1)
+    on = (idx == 0) | (idx == n)
+    kk, jj, ii = np.meshgrid(on, on, on, indexing="ij")
+    node = (ii | jj | kk).ravel().astype(np.uint8)
+    return np.repeat(node, 3)
+
+
+def fd_element_picks(n_el: int, count: int = 64, seed: int = 40) -> np.ndarray:
+    """Element ids for the finite-difference gradient check."""
+    return np.sort(np.random.default_rng(seed).choice(n_el, count, replace=False))
