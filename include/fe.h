@@ -1,0 +1,214 @@
+/*
+ * fe.h -- C ABI of the MI355X element-level finite-element hot path.
+ *
+ * The library computes, for a two-phase (or multi-phase) micromechanics RVE on
+ * a structured n x n x n mesh of 8-node bricks covering the unit cube, the
+ * pieces of the paper's Newton method for R(u) = 0 (Sec. II-A):
+ *   - element residuals assembled into R(u)            (fe_residual)
+ *   - element Jacobians assembled into a sparse K(u)   (fe_csr_indices, fe_tangent_csr;
+ *     the sorted, duplicate-combined sparse tuple of Sec. III-B)
+ *   - the matrix-free action y = K(u) x                 (fe_apply_matfree; Sec. III-A)
+ *   - the sparse mat-vec with the explicit matrix       (fe_apply_csr; Fig. 3)
+ *   - a Jacobi-preconditioned CG solve in FP64 scalars  (fe_pcg; Fig. 4)
+ *   - Newton load stepping around them                  (fe_newton; Sec. II-A, Sec. V-A)
+ *   - the vector-Jacobian product of the residual with respect to a per-element
+ *     modulus scale, for adjoint gradients               (fe_vjp)
+ *
+ * Mesh conventions (fixed): node (i,j,k) has id i + (n+1)(j + (n+1)k) at
+ * x = (i,j,k)/n; element (a,b,c) has id a + n(b + nc); dof = 3*node + comp.
+ * 2x2x2 Gauss points, point q = qx + 2 qy + 4 qz.
+ *
+ * Conventions of every call:
+ *   - Array arguments are DEVICE pointers unless the name ends in _host.  The
+ *     caller owns them; the library only borrows them for the duration of the
+ *     call (and of the work it enqueues).
+ *   - Floating-point arrays are double when the problem was created with
+ *     FE_F64 and float with FE_F32 ("real" below).  Solver scalars and
+ *     reductions are always double.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *     enqueued on it; outputs are valid once the stream has reached that point.
+ *     Calls that return host values (fe_csr_nnz, fe_pcg, fe_newton,
+ *     fe_read_flags) synchronise the stream.
+ *   - Every call returns an fe_status; arguments are validated before anything
+ *     is enqueued; a failing HIP call maps to FE_ERR_HIP and fe_last_error()
+ *     (thread-local) holds the message.  Nothing aborts.
+ *   - Plastic state arrays are SoA with 7 components [eps_p xx,yy,zz,yz,xz,xy
+ *     (engineering shears), alpha], each laid out [q][element]: entry
+ *     (comp, q, e) is at ((comp*8 + q) * n_el + e).
+ */
+#ifndef FE_H
+#define FE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FE_OK = 0,
+  FE_ERR_ARG = 1,           /* invalid argument or unsupported combination */
+  FE_ERR_HIP = 2,           /* a HIP runtime call failed */
+  FE_ERR_OOM = 3,           /* device allocation failed */
+  FE_ERR_NOT_CONVERGED = 4, /* iteration limit reached */
+  FE_ERR_BREAKDOWN = 5,     /* CG found p.Ap <= 0 (operator not SPD) */
+  FE_ERR_NONFINITE = 6,     /* NaN or Inf met in a solver scalar */
+  FE_ERR_INVERTED = 7,      /* an element has det F <= 0 (finite strain) */
+  FE_ERR_STATE = 8          /* call made before the state it needs exists */
+} fe_status;
+
+enum { FE_F64 = 0, FE_F32 = 1 };                      /* precision of real arrays */
+enum { FE_LINEAR = 0, FE_J2 = 1, FE_NEOHOOKE = 2 };    /* constitutive model per phase */
+enum { FE_OP_CSR = 0, FE_OP_MATFREE = 1 };             /* operator used by fe_pcg / fe_newton */
+enum { FE_APPLY_BC = 1, FE_STORE_TANGENT = 2 };        /* fe_residual flags */
+enum { FE_MAX_PHASES = 8 };
+
+typedef struct fe_problem fe_problem;
+
+typedef struct {
+  int iterations;        /* CG iterations performed */
+  int status;            /* fe_status of the solve */
+  double relres;         /* recursive ||r|| / ||b|| at exit */
+  double bnorm;          /* ||b||_2 */
+} fe_pcg_info;
+
+typedef struct {
+  int op;                /* FE_OP_CSR or FE_OP_MATFREE: operator used inside CG */
+  int assemble_csr;      /* with FE_OP_MATFREE: 1 = also assemble the CSR tangent every
+                            iteration (matrix-explicit Jacobian, Sec. III-B) and take the
+                            Jacobi diagonal from it; 0 = diagonal from the element kernel */
+  int max_newton;        /* Newton iterations per load step (e.g. 20) */
+  double newton_rtol;    /* stop when ||P_f R|| <= newton_rtol * ||P_f R||_first (e.g. 1e-8) */
+  double pcg_rtol;       /* inner CG tolerance (e.g. 1e-10) */
+  int pcg_max_it;        /* inner CG iteration limit */
+} fe_newton_opts;
+
+typedef struct {
+  int newton_iterations; /* summed over load steps */
+  int pcg_iterations;    /* summed over all linear solves */
+  int operator_applies;  /* K*x applications (one per CG iteration plus one per solve) */
+  int steps_done;        /* load steps that converged */
+  int status;            /* fe_status of the whole run */
+  double last_residual;  /* ||P_f R|| at the end of the last step */
+} fe_newton_info;
+
+/* Create the structured problem: n elements per side of [0,1]^3 (1 <= n <= 1024,
+ * with 3(n+1)^3 dofs and 9(3n+1)^3 matrix entries both below 2^31), precision
+ * FE_F64 or FE_F32, on the current HIP device.  *out receives an opaque handle
+ * owned by the library (free with fe_problem_destroy). */
+int fe_problem_create(fe_problem** out, int n, int precision);
+void fe_problem_destroy(fe_problem* p);
+
+/* Sizes: out_host[0..5] = n, n_el, n_nodes, n_dof, n_qp (= 8 n_el), nnz. */
+int fe_problem_sizes(const fe_problem* p, int64_t* out_host);
+
+/* Materials (the phase-dependent laws of Sec. V-A).  phase: uint8 [n_el] with
+ * values < n_phases; models_host: [n_phases] FE_LINEAR / FE_J2 / FE_NEOHOOKE;
+ * params_host: [n_phases][4] = {E, nu, sigma_y, H} (the last two used by J2
+ * only); scale: real [n_el] multiplying the elastic moduli of each element, or
+ * NULL for 1.  Phase and scale are copied into library memory. */
+int fe_set_materials(fe_problem* p, const uint8_t* phase, int n_phases, const int* models_host,
+                     const double* params_host, const void* scale, void* stream);
+
+/* Dirichlet dofs: uint8 [n_dof], 1 = constrained (copied).  Default: none. */
+int fe_set_dirichlet(fe_problem* p, const uint8_t* mask, void* stream);
+
+/* u[d] = (eps_bar . x)_comp on constrained dofs d; free dofs keep their value
+ * (zero_free = 0) or are set to 0 (zero_free = 1).  eps_bar_host: 3x3 row-major. */
+int fe_lift(fe_problem* p, const double* eps_bar_host, void* u, int zero_free, void* stream);
+
+/* Residual R(u) = sum_e A_e^T r_e (Sec. II-A).  u, r: real [n_dof].
+ * state_in: plastic state at the last converged step (NULL = zero); state_out:
+ * trial state written for J2 points (NULL = not written).  flags: FE_APPLY_BC
+ * zeroes r on constrained dofs; FE_STORE_TANGENT records the linearisation at u
+ * (J2 consistent tangent per point, Neo-Hookean deformation per point) for
+ * fe_apply_matfree / fe_diagonal / fe_pcg. */
+int fe_residual(fe_problem* p, const void* u, const void* state_in, void* state_out, void* r,
+                int flags, void* stream);
+
+/* Number of stored entries of the sparse Jacobian (structural pattern: every
+ * pair of dofs that share an element, explicit zeros kept): 9(3n+1)^3. */
+int fe_csr_nnz(const fe_problem* p, int64_t* nnz_host);
+
+/* CSR pattern, rows = dofs, columns ascending: row_ptr int32 [n_dof+1],
+ * col_idx int32 [nnz]; identical to sorting all element (row, col) pairs and
+ * combining duplicates (Sec. III-B). */
+int fe_csr_indices(fe_problem* p, int32_t* row_ptr, int32_t* col_idx, void* stream);
+
+/* Jacobian values K(u) in the pattern of fe_csr_indices: vals real [nnz],
+ * duplicates summed.  Linearises at (u, state_in) first (as FE_STORE_TANGENT).
+ * apply_bc = 1 zeroes constrained rows and columns and puts 1 on their diagonal. */
+int fe_tangent_csr(fe_problem* p, const void* u, const void* state_in, void* vals, int apply_bc,
+                   void* stream);
+
+/* Matrix-free y = K x at the stored linearisation (the elastic K when the
+ * problem has only linear phases).  apply_bc = 1 gives P_f K P_f x + P_b x. */
+int fe_apply_matfree(fe_problem* p, const void* x, void* y, int apply_bc, void* stream);
+
+/* CSR y = A x for any CSR matrix with n_dof rows (row_ptr, col_idx int32). */
+int fe_apply_csr(fe_problem* p, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
+                 const void* x, void* y, void* stream);
+
+/* Diagonal of the (masked, if apply_bc) matrix-free operator: d real [n_dof]. */
+int fe_diagonal(fe_problem* p, void* d, int apply_bc, void* stream);
+
+/* Jacobi-preconditioned CG on A x = b (Fig. 4): A is the masked operator
+ * P_f K P_f + P_b, matrix-free (op = FE_OP_MATFREE, CSR arguments ignored) or the
+ * CSR matrix given (op = FE_OP_CSR, already eliminated).  x0 = 0; stops when
+ * ||r||_2 <= rtol ||b||_2.  x: real [n_dof] output.  info_host may be NULL.
+ * Returns FE_OK, FE_ERR_NOT_CONVERGED, FE_ERR_BREAKDOWN or FE_ERR_NONFINITE. */
+int fe_pcg(fe_problem* p, int op, const int32_t* row_ptr, const int32_t* col_idx,
+           const void* vals, const void* b, void* x, double rtol, int max_it,
+           fe_pcg_info* info_host, void* stream);
+
+/* Vector-Jacobian product with respect to the per-element modulus scale s_e:
+ * out[e] = lambda_e^T d r_e / d s_e, real [n_el].  Supported for linear and
+ * Neo-Hookean phases (r_e is proportional to s_e); FE_ERR_ARG with J2 phases. */
+int fe_vjp(fe_problem* p, const void* u, const void* lambda, void* out, void* stream);
+
+/* Newton load stepping: for each of n_steps macro strains (load_path_host:
+ * [n_steps][3][3] row-major) lift the boundary, iterate Newton with the chosen
+ * operator until the opts tolerance, then commit the plastic state.
+ * u: real [n_dof] in/out (the starting field); state: real [7][8][n_el] in/out
+ * (NULL for problems without J2 phases); sigma_bar_host: [n_steps][6] volume
+ * averaged stress after each step, or NULL. */
+int fe_newton(fe_problem* p, const double* load_path_host, int n_steps, const fe_newton_opts* opts,
+              void* u, void* state, double* sigma_bar_host, fe_newton_info* info_host,
+              void* stream);
+
+/* Volume-averaged stress (1/V) sum_q w_q detJ_q sigma_q at (u, state_in),
+ * written to sigma_host[6] in Voigt order [xx,yy,zz,yz,xz,xy]. */
+int fe_mean_stress(fe_problem* p, const void* u, const void* state_in, double* sigma_host,
+                   void* stream);
+
+/* Kernel timing for measurement.  While enabled, the library records a HIP
+ * event pair on the call's stream around each launch of: class 0 the
+ * matrix-free operator kernel (fe_apply_matfree and inside CG), class 1 the CSR
+ * mat-vec (fe_apply_csr and inside CG), class 2 the residual / return-map
+ * element kernel, class 3 the CSR tangent kernel.  enable = 1 clears previous
+ * records; enable = 0 stops recording.  fe_profile_read synchronises the
+ * device and writes, for c = 0..3, out_host[3*c] = launches, out_host[3*c+1] =
+ * summed milliseconds, out_host[3*c+2] = summed algorithmic bytes of those
+ * launches for classes 0 and 1 (compulsory traffic: x read and y written once,
+ * phase ids, the stored tangent values the kernel must read at the current
+ * linearisation; CSR: values, column indices, row pointers, x and y once),
+ * 0 for classes 2 and 3; then clears the records. */
+int fe_profile(fe_problem* p, int enable);
+int fe_profile_read(fe_problem* p, double* out_host);
+
+/* Statistics of the stored linearisation: out_host[0] = Gauss points of J2
+ * phases, out_host[1] = those that were plastic (synchronises). */
+int fe_linearization_stats(fe_problem* p, int64_t* out_host, void* stream);
+
+/* Device-side error flags raised by element kernels since the last read
+ * (bit 0: inverted element).  Synchronises and clears. */
+int fe_read_flags(fe_problem* p, int* flags_host, void* stream);
+
+const char* fe_status_string(int status);
+const char* fe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FE_H */

@@ -1,0 +1,659 @@
+// Host side of libfe: the extern "C" entry points declared in include/fe.h.
+// Argument checks happen before anything is enqueued; HIP failures become
+// FE_ERR_HIP with the runtime's message kept in a thread-local string.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fe_internal.hpp"
+
+namespace fe {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? FE_ERR_OOM : FE_ERR_HIP;
+}
+
+size_t real_size(const fe_problem* p) { return p->prec == FE_F64 ? sizeof(double) : sizeof(float); }
+
+static int arg_error(const char* msg) {
+  set_error(msg);
+  return FE_ERR_ARG;
+}
+
+}  // namespace fe
+
+using namespace fe;
+
+#define HIPCHK(x)                                  \
+  do {                                             \
+    hipError_t _e = (x);                           \
+    if (_e != hipSuccess) return hip_fail(_e, #x); \
+  } while (0)
+
+#define CHKP(p)                                           \
+  do {                                                    \
+    if (!(p)) return arg_error("null problem handle");    \
+  } while (0)
+
+static hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+static int alloc(void** ptr, size_t bytes) {
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    return hip_fail(e, "hipMalloc");
+  }
+  return FE_OK;
+}
+
+static void free_dev(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+// Kernel timing: an event pair on the launch stream around one launch.
+static int prof_begin(fe_problem* p, hipStream_t s, long* idx) {
+  *idx = -1;
+  if (!p->prof) return FE_OK;
+  while (p->ev_used + 2 > p->ev_pool.size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    p->ev_pool.push_back(e);
+  }
+  *idx = (long)p->ev_used;
+  p->ev_used += 2;
+  HIPCHK(hipEventRecord(p->ev_pool[*idx], s));
+  return FE_OK;
+}
+
+static int prof_end(fe_problem* p, hipStream_t s, long idx, int cls) {
+  if (idx < 0) return FE_OK;
+  HIPCHK(hipEventRecord(p->ev_pool[idx + 1], s));
+  p->prof_recs.push_back({cls, (size_t)idx});
+  return FE_OK;
+}
+
+static int operator_bytes(fe_problem* p, int op, hipStream_t s, double* bytes);
+
+#define PROF(p, s, cls, launch_expr)          \
+  do {                                        \
+    long _pi;                                 \
+    if (int _st = prof_begin(p, s, &_pi)) return _st; \
+    HIPCHK(launch_expr);                      \
+    if (int _st = prof_end(p, s, _pi, cls)) return _st; \
+  } while (0)
+
+extern "C" {
+
+const char* fe_status_string(int status) {
+  switch (status) {
+    case FE_OK: return "ok";
+    case FE_ERR_ARG: return "invalid argument";
+    case FE_ERR_HIP: return "HIP runtime error";
+    case FE_ERR_OOM: return "out of device memory";
+    case FE_ERR_NOT_CONVERGED: return "iteration limit reached";
+    case FE_ERR_BREAKDOWN: return "CG breakdown (p.Ap <= 0)";
+    case FE_ERR_NONFINITE: return "non-finite value";
+    case FE_ERR_INVERTED: return "inverted element (det F <= 0)";
+    case FE_ERR_STATE: return "required state missing";
+    default: return "unknown status";
+  }
+}
+
+const char* fe_last_error(void) { return g_last_error.c_str(); }
+
+void fe_problem_destroy(fe_problem* p) {
+  if (!p) return;
+  free_dev(p->phase);
+  free_dev(p->scale);
+  free_dev(p->mask);
+  free_dev(p->tangent);
+  free_dev(p->u_lin);
+  free_dev(p->w_r);
+  free_dev(p->w_p);
+  free_dev(p->w_q);
+  free_dev(p->w_d);
+  free_dev(p->w_v);
+  free_dev(p->w_v2);
+  free_dev(p->w_state);
+  free_dev(p->partials);
+  free_dev(p->counter);
+  free_dev(p->ctrl);
+  free_dev(p->stress_sum);
+  free_dev(p->flags);
+  free_dev(p->csr_rp);
+  free_dev(p->csr_ci);
+  free_dev(p->csr_v);
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  if (p->host_ctrl) (void)hipHostFree(p->host_ctrl);
+  if (p->host_buf) (void)hipHostFree(p->host_buf);
+  delete p;
+}
+
+int fe_problem_create(fe_problem** out, int n, int precision) {
+  if (!out) return arg_error("out is null");
+  *out = nullptr;
+  if (n < 1 || n > 1024) return arg_error("n must be in [1, 1024]");
+  if (precision != FE_F64 && precision != FE_F32) return arg_error("precision must be FE_F64 or FE_F32");
+  const int64_t np1 = n + 1;
+  if (3 * np1 * np1 * np1 >= (int64_t(1) << 31)) return arg_error("too many dofs for 32-bit indexing");
+  fe_problem* p = new fe_problem();
+  p->n = n;
+  p->prec = precision;
+  p->n_el = (int64_t)n * n * n;
+  p->n_nodes = np1 * np1 * np1;
+  p->n_dof = 3 * p->n_nodes;
+  const int64_t t = 3 * (int64_t)n + 1;
+  p->nnz = 9 * t * t * t;
+  p->h = 1.0 / n;
+  HIPCHK(hipGetDevice(&p->device));
+  const size_t rs = real_size(p), vec = rs * p->n_dof;
+  int st = FE_OK;
+  if ((st = alloc((void**)&p->phase, p->n_el)) || (st = alloc(&p->w_r, vec)) || (st = alloc(&p->w_p, vec)) ||
+      (st = alloc(&p->w_q, vec)) || (st = alloc(&p->w_d, vec)) ||
+      (st = alloc((void**)&p->partials, 2 * 1024 * sizeof(double))) ||
+      (st = alloc((void**)&p->counter, sizeof(unsigned int))) || (st = alloc((void**)&p->ctrl, sizeof(CgCtrl))) ||
+      (st = alloc((void**)&p->stress_sum, 8 * sizeof(double))) || (st = alloc((void**)&p->flags, sizeof(int)))) {
+    fe_problem_destroy(p);
+    return st;
+  }
+  hipError_t e;
+  if ((e = hipMemset(p->phase, 0, p->n_el)) != hipSuccess || (e = hipMemset(p->counter, 0, sizeof(unsigned int))) ||
+      (e = hipMemset(p->flags, 0, sizeof(int))) || (e = hipMemset(p->ctrl, 0, sizeof(CgCtrl))) ||
+      (e = hipHostMalloc((void**)&p->host_ctrl, sizeof(CgCtrl), hipHostMallocDefault)) ||
+      (e = hipHostMalloc((void**)&p->host_buf, 64 * sizeof(double), hipHostMallocDefault))) {
+    fe_problem_destroy(p);
+    return hip_fail(e, "fe_problem_create");
+  }
+  // default material: one linear phase with E = 1, nu = 0.3
+  p->mat.n = 1;
+  p->mat.ph[0] = PhaseConst{FE_LINEAR, 1.0 * 0.3 / (1.3 * 0.4), 1.0 / 2.6, 1.0 / 1.2, 1.0 / 2.6, 0, 0};
+  *out = p;
+  return FE_OK;
+}
+
+int fe_problem_sizes(const fe_problem* p, int64_t* out) {
+  CHKP(p);
+  if (!out) return arg_error("out is null");
+  out[0] = p->n;
+  out[1] = p->n_el;
+  out[2] = p->n_nodes;
+  out[3] = p->n_dof;
+  out[4] = 8 * p->n_el;
+  out[5] = p->nnz;
+  return FE_OK;
+}
+
+int fe_set_materials(fe_problem* p, const uint8_t* phase, int n_phases, const int* models, const double* params,
+                     const void* scale, void* stream) {
+  CHKP(p);
+  if (!phase || !models || !params) return arg_error("phase, models and params are required");
+  if (n_phases < 1 || n_phases > FE_MAX_PHASES) return arg_error("n_phases out of range");
+  Phases m{};
+  m.n = n_phases;
+  bool j2 = false, nh = false;
+  for (int i = 0; i < n_phases; ++i) {
+    const double E = params[4 * i], nu = params[4 * i + 1], sy = params[4 * i + 2], H = params[4 * i + 3];
+    if (models[i] < FE_LINEAR || models[i] > FE_NEOHOOKE) return arg_error("unknown model");
+    if (!(nu > -1.0 && nu < 0.5) || !std::isfinite(E)) return arg_error("invalid E or nu");
+    if (models[i] == FE_J2 && !(sy > 0 && H >= 0)) return arg_error("J2 needs sigma_y > 0 and H >= 0");
+    PhaseConst c;
+    c.model = models[i];
+    c.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    c.mu = E / (2.0 * (1.0 + nu));
+    c.K = E / (3.0 * (1.0 - 2.0 * nu));
+    c.G = c.mu;
+    c.sy = sy;
+    c.H = H;
+    m.ph[i] = c;
+    j2 |= models[i] == FE_J2;
+    nh |= models[i] == FE_NEOHOOKE;
+  }
+  if (j2 && nh) return arg_error("J2 and Neo-Hookean phases cannot be mixed in one problem");
+  const size_t rs = real_size(p);
+  {  // every phase id must index the table: checked on the host before any kernel reads it
+    std::vector<uint8_t> h(p->n_el);
+    HIPCHK(hipMemcpyAsync(h.data(), phase, p->n_el, hipMemcpyDeviceToHost, S(stream)));
+    HIPCHK(hipStreamSynchronize(S(stream)));
+    for (uint8_t v : h)
+      if (v >= n_phases) return arg_error("phase id >= n_phases");
+  }
+  HIPCHK(hipMemcpyAsync(p->phase, phase, p->n_el, hipMemcpyDeviceToDevice, S(stream)));
+  if (scale) {
+    if (!p->scale) {
+      int st = alloc(&p->scale, rs * p->n_el);
+      if (st) return st;
+    }
+    HIPCHK(hipMemcpyAsync(p->scale, scale, rs * p->n_el, hipMemcpyDeviceToDevice, S(stream)));
+  } else if (p->scale) {
+    free_dev(p->scale);
+    p->scale = nullptr;
+  }
+  const int comps = nh ? 10 : (j2 ? 6 : 0);
+  if (comps) {
+    free_dev(p->tangent);
+    p->tangent = nullptr;
+    int st = alloc(&p->tangent, rs * comps * 8 * p->n_el);
+    if (st) return st;
+  }
+  if (nh && !p->u_lin) {
+    int st = alloc(&p->u_lin, rs * p->n_dof);
+    if (st) return st;
+  }
+  p->mat = m;
+  p->model_set = j2 ? MS_J2 : (nh ? MS_NH : MS_LINEAR);
+  p->materials_set = true;
+  p->lin_valid = !(j2 || nh);
+  return FE_OK;
+}
+
+int fe_set_dirichlet(fe_problem* p, const uint8_t* mask, void* stream) {
+  CHKP(p);
+  if (!mask) {
+    free_dev(p->mask);
+    p->mask = nullptr;
+    return FE_OK;
+  }
+  if (!p->mask) {
+    int st = alloc((void**)&p->mask, p->n_dof);
+    if (st) return st;
+  }
+  HIPCHK(hipMemcpyAsync(p->mask, mask, p->n_dof, hipMemcpyDeviceToDevice, S(stream)));
+  return FE_OK;
+}
+
+int fe_lift(fe_problem* p, const double* eps_bar, void* u, int zero_free, void* stream) {
+  CHKP(p);
+  if (!eps_bar || !u) return arg_error("eps_bar and u are required");
+  HIPCHK(launch_lift(p, eps_bar, u, zero_free, S(stream)));
+  return FE_OK;
+}
+
+static ElemArgs base_args(const fe_problem* p) {
+  ElemArgs a{};
+  a.n = p->n;
+  a.h = p->h;
+  a.n_el = p->n_el;
+  a.phase = p->phase;
+  a.scale = p->scale;
+  a.mask = p->mask;
+  a.tangent = p->tangent;
+  a.flags = p->flags;
+  a.mat = p->mat;
+  return a;
+}
+
+static int residual_impl(fe_problem* p, const void* u, const void* state_in, void* state_out, void* r, int flags,
+                         double* stress_sum, hipStream_t s) {
+  const size_t rs = real_size(p);
+  if (r) HIPCHK(launch_fill(p, r, p->n_dof, 0.0, s));
+  ElemArgs a = base_args(p);
+  a.x = u;
+  a.y = r;
+  a.state_in = state_in;
+  a.state_out = state_out;
+  a.store_tangent = (flags & FE_STORE_TANGENT) ? 1 : 0;
+  a.apply_bc = (flags & FE_APPLY_BC) ? 1 : 0;
+  a.stress_sum = stress_sum;
+  PROF(p, s, 2, launch_elem(p, OP_RESID, a, s));
+  if (a.store_tangent) {
+    if (p->model_set == MS_NH) HIPCHK(hipMemcpyAsync(p->u_lin, u, rs * p->n_dof, hipMemcpyDeviceToDevice, s));
+    p->lin_valid = true;
+  }
+  return FE_OK;
+}
+
+int fe_residual(fe_problem* p, const void* u, const void* state_in, void* state_out, void* r, int flags,
+                void* stream) {
+  CHKP(p);
+  if (!u || !r) return arg_error("u and r are required");
+  if (state_out && p->model_set != MS_J2) state_out = nullptr;
+  return residual_impl(p, u, state_in, state_out, r, flags, nullptr, S(stream));
+}
+
+int fe_mean_stress(fe_problem* p, const void* u, const void* state_in, double* sigma, void* stream) {
+  CHKP(p);
+  if (!u || !sigma) return arg_error("u and sigma are required");
+  HIPCHK(hipMemsetAsync(p->stress_sum, 0, 6 * sizeof(double), S(stream)));
+  int st = residual_impl(p, u, state_in, nullptr, nullptr, 0, p->stress_sum, S(stream));
+  if (st) return st;
+  HIPCHK(hipMemcpyAsync(p->host_buf, p->stress_sum, 6 * sizeof(double), hipMemcpyDeviceToHost, S(stream)));
+  HIPCHK(hipStreamSynchronize(S(stream)));
+  for (int k = 0; k < 6; ++k) sigma[k] = p->host_buf[k];  // unit-cube volume
+  return FE_OK;
+}
+
+int fe_csr_nnz(const fe_problem* p, int64_t* nnz) {
+  CHKP(p);
+  if (!nnz) return arg_error("nnz is null");
+  *nnz = p->nnz;
+  return FE_OK;
+}
+
+static int check_csr_size(const fe_problem* p) {
+  if (p->nnz >= (int64_t(1) << 31)) return arg_error("matrix too large for int32 CSR indices");
+  return FE_OK;
+}
+
+int fe_csr_indices(fe_problem* p, int32_t* row_ptr, int32_t* col_idx, void* stream) {
+  CHKP(p);
+  if (!row_ptr || !col_idx) return arg_error("row_ptr and col_idx are required");
+  if (int st = check_csr_size(p)) return st;
+  HIPCHK(launch_csr_pattern(p, row_ptr, col_idx, S(stream)));
+  return FE_OK;
+}
+
+int fe_tangent_csr(fe_problem* p, const void* u, const void* state_in, void* vals, int apply_bc, void* stream) {
+  CHKP(p);
+  if (!u || !vals) return arg_error("u and vals are required");
+  if (int st = check_csr_size(p)) return st;
+  if (p->model_set != MS_LINEAR) {
+    int st = residual_impl(p, u, state_in, nullptr, nullptr, FE_STORE_TANGENT, nullptr, S(stream));
+    if (st) return st;
+  }
+  PROF(p, S(stream), 3, launch_tangent_csr(p, vals, apply_bc, S(stream)));
+  return FE_OK;
+}
+
+int fe_apply_matfree(fe_problem* p, const void* x, void* y, int apply_bc, void* stream) {
+  CHKP(p);
+  if (!x || !y) return arg_error("x and y are required");
+  if (!p->lin_valid) {
+    set_error("no linearisation stored: call fe_residual with FE_STORE_TANGENT or fe_tangent_csr first");
+    return FE_ERR_STATE;
+  }
+  HIPCHK(launch_fill(p, y, p->n_dof, 0.0, S(stream)));
+  ElemArgs a = base_args(p);
+  a.x = x;
+  a.xlin = p->u_lin;
+  a.y = y;
+  a.apply_bc = apply_bc ? 1 : 0;
+  PROF(p, S(stream), 0, launch_elem(p, OP_APPLY, a, S(stream)));
+  if (p->prof) {
+    double b = 0;
+    if (int e = operator_bytes(p, FE_OP_MATFREE, S(stream), &b)) return e;
+    p->prof_bytes[0] += b;
+  }
+  return FE_OK;
+}
+
+int fe_apply_csr(fe_problem* p, const int32_t* row_ptr, const int32_t* col_idx, const void* vals, const void* x,
+                 void* y, void* stream) {
+  CHKP(p);
+  if (!row_ptr || !col_idx || !vals || !x || !y) return arg_error("all CSR arrays and vectors are required");
+  PROF(p, S(stream), 1, launch_spmv(p, row_ptr, col_idx, vals, x, y, S(stream)));
+  if (p->prof) {
+    double b = 0;
+    if (int e = operator_bytes(p, FE_OP_CSR, S(stream), &b)) return e;
+    p->prof_bytes[1] += b;
+  }
+  return FE_OK;
+}
+
+int fe_diagonal(fe_problem* p, void* d, int apply_bc, void* stream) {
+  CHKP(p);
+  if (!d) return arg_error("d is required");
+  if (!p->lin_valid) {
+    set_error("no linearisation stored");
+    return FE_ERR_STATE;
+  }
+  HIPCHK(launch_diag(p, d, apply_bc, S(stream)));
+  return FE_OK;
+}
+
+}  // extern "C"
+
+// CG driver: kernels run with device-side scalars; the host checks the status
+// word every `chunk` iterations (iterations after convergence are no-ops).
+// The Jacobi diagonal comes from the CSR matrix when one is given (rp != null),
+// else from the element kernel; `op` selects the operator inside the iteration.
+static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, const void* b,
+                   void* x, double rtol, int max_it, fe_pcg_info* info, hipStream_t s, int* applies) {
+  if (rp) {
+    HIPCHK(launch_csr_diag(p, rp, ci, vals, p->w_d, s));
+  } else {
+    HIPCHK(launch_diag(p, p->w_d, 1, s));
+  }
+  HIPCHK(cg_init(p, b, x, rtol, max_it, s));
+  const size_t rec0 = p->prof_recs.size();
+  const int cls = op == FE_OP_CSR ? 1 : 0;
+  int launched = 0, chunk = 8;
+  for (;;) {
+    for (int k = 0; k < chunk; ++k) {
+      PROF(p, s, cls, cg_operator(p, op, rp, ci, vals, s));
+      HIPCHK(cg_vectors(p, x, s));
+    }
+    launched += chunk;
+    HIPCHK(hipMemcpyAsync(p->host_ctrl, p->ctrl, sizeof(CgCtrl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (p->host_ctrl->status != CG_RUNNING || launched > max_it + 64) break;
+    if (chunk < 32) chunk *= 2;
+  }
+  const CgCtrl& c = *p->host_ctrl;
+  const int status = c.status == CG_RUNNING ? FE_ERR_NOT_CONVERGED : (c.status == CG_CONVERGED ? FE_OK : c.status);
+  // operator launches after the stopping iteration returned at once: drop their timings
+  const size_t executed = (size_t)c.iters + (status == FE_ERR_BREAKDOWN || status == FE_ERR_NONFINITE ? 1 : 0);
+  if (p->prof) {
+    if (p->prof_recs.size() > rec0 + executed) p->prof_recs.resize(rec0 + executed);
+    double b = 0;
+    if (int e = operator_bytes(p, op, s, &b)) return e;
+    p->prof_bytes[cls] += b * (double)executed;
+  }
+  if (info) {
+    info->iterations = c.iters;
+    info->status = status;
+    info->bnorm = std::sqrt(c.bb);
+    info->relres = c.bb > 0 ? std::sqrt(c.rr / c.bb) : 0.0;
+  }
+  if (applies) *applies += c.iters + (status == FE_ERR_BREAKDOWN || status == FE_ERR_NONFINITE ? 1 : 0);
+  if (status != FE_OK) set_error(fe_status_string(status));
+  return status;
+}
+
+extern "C" int fe_pcg(fe_problem* p, int op, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
+                      const void* b, void* x, double rtol, int max_it, fe_pcg_info* info, void* stream) {
+  CHKP(p);
+  if (!b || !x) return arg_error("b and x are required");
+  if (op != FE_OP_CSR && op != FE_OP_MATFREE) return arg_error("op must be FE_OP_CSR or FE_OP_MATFREE");
+  if (op == FE_OP_CSR && (!row_ptr || !col_idx || !vals)) return arg_error("CSR operator needs row_ptr, col_idx, vals");
+  if (op == FE_OP_MATFREE && !p->lin_valid) {
+    set_error("no linearisation stored");
+    return FE_ERR_STATE;
+  }
+  if (!(rtol >= 0) || max_it < 0) return arg_error("rtol must be >= 0 and max_it >= 0");
+  if (op == FE_OP_MATFREE) row_ptr = nullptr, col_idx = nullptr, vals = nullptr;
+  return pcg_run(p, op, row_ptr, col_idx, vals, b, x, rtol, max_it, info, S(stream), nullptr);
+}
+
+extern "C" int fe_vjp(fe_problem* p, const void* u, const void* lambda, void* out, void* stream) {
+  CHKP(p);
+  if (!u || !lambda || !out) return arg_error("u, lambda and out are required");
+  if (p->model_set == MS_J2) return arg_error("fe_vjp supports linear and Neo-Hookean phases only");
+  ElemArgs a = base_args(p);
+  a.x = u;
+  a.xlin = lambda;
+  a.out_el = out;
+  HIPCHK(launch_elem(p, OP_VJP, a, S(stream)));
+  return FE_OK;
+}
+
+extern "C" int fe_read_flags(fe_problem* p, int* flags, void* stream) {
+  CHKP(p);
+  if (!flags) return arg_error("flags is null");
+  int* hb = reinterpret_cast<int*>(p->host_buf);
+  HIPCHK(hipMemcpyAsync(hb, p->flags, sizeof(int), hipMemcpyDeviceToHost, S(stream)));
+  HIPCHK(hipMemsetAsync(p->flags, 0, sizeof(int), S(stream)));
+  HIPCHK(hipStreamSynchronize(S(stream)));
+  *flags = *hb;
+  return FE_OK;
+}
+
+static int read_norm(fe_problem* p, const void* v, hipStream_t s, double* out) {
+  HIPCHK(launch_dot(p, v, v, p->n_dof, p->stress_sum + 6, s));
+  HIPCHK(hipMemcpyAsync(p->host_buf, p->stress_sum + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *out = std::sqrt(p->host_buf[0]);
+  return FE_OK;
+}
+
+extern "C" int fe_newton(fe_problem* p, const double* path, int n_steps, const fe_newton_opts* o, void* u,
+                         void* state, double* sigma_bar, fe_newton_info* info, void* stream) {
+  CHKP(p);
+  if (!path || !o || !u || n_steps < 0) return arg_error("path, opts and u are required");
+  if (o->op != FE_OP_CSR && o->op != FE_OP_MATFREE) return arg_error("opts.op must be FE_OP_CSR or FE_OP_MATFREE");
+  if (o->max_newton < 1 || !(o->newton_rtol >= 0) || !(o->pcg_rtol >= 0) || o->pcg_max_it < 1)
+    return arg_error("invalid Newton options");
+  if (p->model_set == MS_J2 && !state) return arg_error("J2 problems need a state array");
+  hipStream_t s = S(stream);
+  const size_t rs = real_size(p), vec = rs * p->n_dof;
+  if (!p->w_v && alloc(&p->w_v, vec)) return FE_ERR_OOM;
+  if (!p->w_v2 && alloc(&p->w_v2, vec)) return FE_ERR_OOM;
+  if (p->model_set == MS_J2 && !p->w_state && alloc(&p->w_state, rs * 7 * 8 * p->n_el)) return FE_ERR_OOM;
+  const bool use_csr = o->op == FE_OP_CSR || o->assemble_csr;
+  if (use_csr) {
+    if (int st = check_csr_size(p)) return st;
+    if (!p->csr_rp) {
+      if (alloc((void**)&p->csr_rp, sizeof(int32_t) * (p->n_dof + 1)) ||
+          alloc((void**)&p->csr_ci, sizeof(int32_t) * p->nnz) || alloc(&p->csr_v, rs * p->nnz))
+        return FE_ERR_OOM;
+      HIPCHK(launch_csr_pattern(p, p->csr_rp, p->csr_ci, s));
+    }
+  }
+  fe_newton_info inf{};
+  inf.status = FE_OK;
+  void* r = p->w_v;
+  void* w = p->w_v2;
+  void* trial = p->model_set == MS_J2 ? p->w_state : nullptr;
+  for (int step = 0; step < n_steps; ++step) {
+    HIPCHK(launch_lift(p, path + 9 * step, u, 0, s));
+    double r0 = -1.0, rn = 0.0;
+    bool converged = false;
+    for (int it = 0; it <= o->max_newton; ++it) {
+      int st = residual_impl(p, u, state, trial, r, FE_APPLY_BC | FE_STORE_TANGENT, nullptr, s);
+      if (st) return st;
+      if ((st = read_norm(p, r, s, &rn))) return st;
+      int fl = 0;
+      if ((st = fe_read_flags(p, &fl, stream))) return st;
+      if (fl & 1) {
+        set_error("inverted element");
+        inf.status = FE_ERR_INVERTED;
+        break;
+      }
+      if (!std::isfinite(rn)) {
+        set_error("non-finite residual");
+        inf.status = FE_ERR_NONFINITE;
+        break;
+      }
+      if (r0 < 0) r0 = rn;
+      if (rn <= o->newton_rtol * r0 || rn == 0.0) {
+        converged = true;
+        break;
+      }
+      if (it == o->max_newton) break;
+      inf.newton_iterations += 1;
+      HIPCHK(launch_axpby(p, p->n_dof, -1.0, r, 0.0, r, s));  // b = -P_f R
+      const int32_t *rp = nullptr, *ci = nullptr;
+      const void* vals = nullptr;
+      if (use_csr) {
+        PROF(p, s, 3, launch_tangent_csr(p, p->csr_v, 1, s));
+        rp = p->csr_rp;
+        ci = p->csr_ci;
+        vals = p->csr_v;
+      }
+      fe_pcg_info pi{};
+      st = pcg_run(p, o->op, rp, ci, vals, r, w, o->pcg_rtol, o->pcg_max_it, &pi, s, &inf.operator_applies);
+      inf.pcg_iterations += pi.iterations;
+      if (st) {
+        inf.status = st;
+        break;
+      }
+      HIPCHK(launch_axpby(p, p->n_dof, 1.0, w, 1.0, u, s));
+    }
+    inf.last_residual = rn;
+    if (inf.status != FE_OK) break;
+    if (!converged) {
+      inf.status = FE_ERR_NOT_CONVERGED;
+      set_error("Newton did not converge");
+      break;
+    }
+    if (sigma_bar) {  // stress of the converged iterate, from the state the step started from
+      int st = fe_mean_stress(p, u, state, sigma_bar + 6 * step, stream);
+      if (st) return st;
+    }
+    if (trial) HIPCHK(hipMemcpyAsync(state, trial, rs * 7 * 8 * p->n_el, hipMemcpyDeviceToDevice, s));
+    inf.steps_done += 1;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  if (info) *info = inf;
+  return inf.status;
+}
+
+extern "C" int fe_profile(fe_problem* p, int enable) {
+  CHKP(p);
+  if (enable) {
+    p->prof_recs.clear();
+    p->ev_used = 0;
+  }
+  p->prof = enable != 0;
+  return FE_OK;
+}
+
+extern "C" int fe_profile_read(fe_problem* p, double* out) {
+  CHKP(p);
+  if (!out) return arg_error("out is null");
+  for (int k = 0; k < 12; ++k) out[k] = 0;
+  HIPCHK(hipDeviceSynchronize());
+  for (const auto& r : p->prof_recs) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, p->ev_pool[r.second], p->ev_pool[r.second + 1]));
+    out[3 * r.first] += 1;
+    out[3 * r.first + 1] += ms;
+  }
+  for (int c = 0; c < 4; ++c) {
+    out[3 * c + 2] = p->prof_bytes[c];
+    p->prof_bytes[c] = 0;
+  }
+  p->prof_recs.clear();
+  p->ev_used = 0;
+  return FE_OK;
+}
+
+// Algorithmic bytes of one operator launch at the current linearisation.
+static int operator_bytes(fe_problem* p, int op, hipStream_t s, double* bytes) {
+  const double w = (double)real_size(p);
+  if (op == FE_OP_CSR) {
+    *bytes = (w + 4.0) * (double)p->nnz + 4.0 * (double)(p->n_dof + 1) + 2.0 * w * (double)p->n_dof;
+    return FE_OK;
+  }
+  int64_t st[2] = {0, 0};
+  if (p->model_set == MS_J2) {
+    if (int e = fe_linearization_stats(p, st, s)) return e;
+  }
+  // x in, y out, phase ids, and per J2 point the plastic flag word plus 5 more values if plastic
+  double b = 2.0 * w * (double)p->n_dof + (double)p->n_el + w * ((double)st[0] + 5.0 * (double)st[1]);
+  if (p->model_set == MS_NH) b += w * (double)p->n_dof;  // linearisation point gathered as well
+  *bytes = b;
+  return FE_OK;
+}
+
+extern "C" int fe_linearization_stats(fe_problem* p, int64_t* out, void* stream) {
+  CHKP(p);
+  if (!out) return arg_error("out is null");
+  out[0] = out[1] = 0;
+  if (p->model_set != MS_J2 || !p->lin_valid) return FE_OK;
+  unsigned long long* d = reinterpret_cast<unsigned long long*>(p->stress_sum);
+  HIPCHK(hipMemsetAsync(d, 0, 2 * sizeof(unsigned long long), S(stream)));
+  HIPCHK(launch_lin_stats(p, d, S(stream)));
+  HIPCHK(hipMemcpyAsync(p->host_buf, d, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, S(stream)));
+  HIPCHK(hipStreamSynchronize(S(stream)));
+  const unsigned long long* h = reinterpret_cast<const unsigned long long*>(p->host_buf);
+  out[0] = (int64_t)h[0];
+  out[1] = (int64_t)h[1];
+  return FE_OK;
+}

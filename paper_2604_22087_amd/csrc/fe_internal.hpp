@@ -1,0 +1,154 @@
+// Internal declarations shared by the host API and the HIP kernels of libfe.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/fe.h"
+
+namespace fe {
+
+// Per-phase material constants, already converted to the forms kernels use.
+struct PhaseConst {
+  int model;        // FE_LINEAR / FE_J2 / FE_NEOHOOKE
+  double lam, mu;   // Lame parameters (before the per-element scale)
+  double K, G;      // bulk and shear moduli (J2)
+  double sy, H;     // yield stress and linear hardening modulus (J2)
+};
+
+struct Phases {
+  PhaseConst ph[FE_MAX_PHASES];
+  int n;
+};
+
+// Which constitutive models a launch has to handle (selects a kernel instance).
+enum ModelSet { MS_LINEAR = 0, MS_J2 = 1, MS_NH = 2 };
+
+// Element-kernel operations.
+enum ElemOp {
+  OP_RESID = 0,   // r = sum_e A_e^T r_e(u)        (+ state / linearisation side outputs)
+  OP_APPLY = 1,   // y = K_lin x                   (matrix-free)
+  OP_VJP = 2      // out_e = lambda_e . d r_e / d s_e
+};
+
+// CG status word: kernels stop on any non-zero value, so "converged" must differ from 0.
+constexpr int CG_RUNNING = 0;
+constexpr int CG_CONVERGED = -1;
+
+// Device scalar block used by CG (one per problem).
+struct CgCtrl {
+  double rz;        // r.z of the current iterate
+  double pq;        // p.Ap of the current iteration
+  double alpha, beta;
+  double rr;        // ||r||^2
+  double bb;        // ||b||^2
+  double tol2;      // rtol^2 ||b||^2
+  int iters;
+  int status;       // CG_RUNNING, CG_CONVERGED or an fe_status error code
+  int max_it;
+  int pad;
+};
+
+struct ElemArgs {
+  int n;
+  double h;
+  int64_t n_el;
+  const uint8_t* phase;
+  const void* scale;      // real [n_el] or null
+  const uint8_t* mask;    // [n_dof] or null
+  const void* x;          // gathered field (u for RESID/VJP, x for APPLY)
+  const void* xlin;       // Neo-Hookean linearisation point (APPLY) / lambda (VJP)
+  void* y;                // scattered output (may be null for RESID = linearise only)
+  const void* state_in;   // J2 state [7][8][n_el] or null
+  void* state_out;        // J2 trial state or null
+  void* tangent;          // J2 compact tangent [6][8][n_el] (written in RESID, read in APPLY)
+  void* out_el;           // VJP output [n_el]
+  double* stress_sum;     // [6] volume-integrated stress accumulator or null
+  int* flags;             // device error flags
+  int apply_bc;
+  int store_tangent;
+  Phases mat;
+};
+
+template <typename T> struct Buf { T* p = nullptr; };
+
+}  // namespace fe
+
+struct fe_problem {
+  int n = 0;
+  int prec = FE_F64;
+  int64_t n_el = 0, n_nodes = 0, n_dof = 0, nnz = 0;
+  double h = 0;
+  int device = 0;
+  fe::Phases mat{};
+  int model_set = fe::MS_LINEAR;
+  bool materials_set = false;
+  uint8_t* phase = nullptr;   // [n_el]
+  void* scale = nullptr;      // real [n_el] or null
+  uint8_t* mask = nullptr;    // [n_dof] or null
+  void* tangent = nullptr;    // J2 compact tangent [6][8][n_el]
+  void* u_lin = nullptr;      // Neo-Hookean linearisation point [n_dof]
+  bool lin_valid = false;
+  // solver workspace
+  void* w_r = nullptr;
+  void* w_p = nullptr;
+  void* w_q = nullptr;
+  void* w_d = nullptr;        // inverse diagonal
+  void* w_v = nullptr;        // scratch vector (Newton)
+  void* w_v2 = nullptr;       // scratch vector (Newton)
+  void* w_state = nullptr;    // J2 trial state (Newton)
+  double* partials = nullptr; // block partial sums (double)
+  unsigned int* counter = nullptr;
+  fe::CgCtrl* ctrl = nullptr;
+  double* stress_sum = nullptr;
+  int* flags = nullptr;
+  int32_t* csr_rp = nullptr;  // Newton's own CSR (matrix-explicit path)
+  int32_t* csr_ci = nullptr;
+  void* csr_v = nullptr;
+  fe::CgCtrl* host_ctrl = nullptr;  // pinned
+  double* host_buf = nullptr;       // pinned scratch
+  // kernel timing (fe_profile): event pairs around selected launches
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, size_t>> prof_recs;  // (kernel class, index of the start event)
+  size_t ev_used = 0;
+  double prof_bytes[4] = {0, 0, 0, 0};            // algorithmic bytes of the recorded launches
+};
+
+namespace fe {
+
+size_t real_size(const fe_problem* p);
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+// kernel launchers (fe_kernels.hip); each returns hipError_t of the launch
+hipError_t launch_elem(const fe_problem* p, int op, const ElemArgs& a, hipStream_t s);
+hipError_t launch_diag(const fe_problem* p, void* d, int apply_bc, hipStream_t s);
+hipError_t launch_csr_pattern(const fe_problem* p, int32_t* row_ptr, int32_t* col_idx, hipStream_t s);
+hipError_t launch_tangent_csr(const fe_problem* p, void* vals, int apply_bc, hipStream_t s);
+hipError_t launch_spmv(const fe_problem* p, const int32_t* rp, const int32_t* ci, const void* v,
+                       const void* x, void* y, hipStream_t s);
+hipError_t launch_fill(const fe_problem* p, void* x, int64_t n, double v, hipStream_t s);
+hipError_t launch_lift(const fe_problem* p, const double* eps, void* u, int zero_free, hipStream_t s);
+hipError_t launch_axpby(const fe_problem* p, int64_t n, double a, const void* x, double b, void* y,
+                        hipStream_t s);
+hipError_t launch_mask_zero(const fe_problem* p, void* x, hipStream_t s);
+hipError_t launch_dot(const fe_problem* p, const void* a, const void* b, int64_t n, double* out,
+                      hipStream_t s);
+hipError_t launch_csr_diag(const fe_problem* p, const int32_t* rp, const int32_t* ci, const void* v, void* d,
+                           hipStream_t s);
+hipError_t launch_copy_cvt(const fe_problem* p, const void* src, void* dst, int64_t n, hipStream_t s);
+
+hipError_t launch_lin_stats(const fe_problem* p, unsigned long long* out, hipStream_t s);
+
+// CG pieces: one iteration = cg_operator (q = A p) then cg_vectors (scalars and updates)
+hipError_t cg_init(const fe_problem* p, const void* b, void* x, double rtol, int max_it, hipStream_t s);
+hipError_t cg_operator(const fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals,
+                       hipStream_t s);
+hipError_t cg_vectors(const fe_problem* p, void* x, hipStream_t s);
+
+}  // namespace fe

@@ -1,0 +1,300 @@
+"""Thin Python binding of libfe (include/fe.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts torch device
+tensors to raw pointers, passes the current torch stream as the hipStream_t and
+turns non-zero statuses into FeError.  There is no CPU fallback: if libfe.so is
+missing or no GPU is visible, calls fail.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfe.so")
+
+F64, F32 = 0, 1
+LINEAR, J2, NEOHOOKE = 0, 1, 2
+OP_CSR, OP_MATFREE = 0, 1
+APPLY_BC, STORE_TANGENT = 1, 2
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "HIP runtime error", 3: "out of device memory",
+          4: "iteration limit reached", 5: "CG breakdown", 6: "non-finite value",
+          7: "inverted element", 8: "required state missing"}
+
+_vp, _i32, _i64, _dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+
+
+class PcgInfo(ctypes.Structure):
+    _fields_ = [("iterations", _i32), ("status", _i32), ("relres", _dbl), ("bnorm", _dbl)]
+
+
+class NewtonOpts(ctypes.Structure):
+    _fields_ = [("op", _i32), ("assemble_csr", _i32), ("max_newton", _i32), ("newton_rtol", _dbl), ("pcg_rtol", _dbl),
+                ("pcg_max_it", _i32)]
+
+
+class NewtonInfo(ctypes.Structure):
+    _fields_ = [("newton_iterations", _i32), ("pcg_iterations", _i32), ("operator_applies", _i32),
+                ("steps_done", _i32), ("status", _i32), ("last_residual", _dbl)]
+
+
+# (name, restype, argtypes) of every exported entry point
+SIGNATURES = [
+    ("fe_problem_create", _i32, [ctypes.POINTER(_vp), _i32, _i32]),
+    ("fe_problem_destroy", None, [_vp]),
+    ("fe_problem_sizes", _i32, [_vp, ctypes.POINTER(_i64)]),
+    ("fe_set_materials", _i32, [_vp, _vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_dbl), _vp, _vp]),
+    ("fe_set_dirichlet", _i32, [_vp, _vp, _vp]),
+    ("fe_lift", _i32, [_vp, ctypes.POINTER(_dbl), _vp, _i32, _vp]),
+    ("fe_residual", _i32, [_vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    ("fe_csr_nnz", _i32, [_vp, ctypes.POINTER(_i64)]),
+    ("fe_csr_indices", _i32, [_vp, _vp, _vp, _vp]),
+    ("fe_tangent_csr", _i32, [_vp, _vp, _vp, _vp, _i32, _vp]),
+    ("fe_apply_matfree", _i32, [_vp, _vp, _vp, _i32, _vp]),
+    ("fe_apply_csr", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    ("fe_diagonal", _i32, [_vp, _vp, _i32, _vp]),
+    ("fe_pcg", _i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _dbl, _i32, ctypes.POINTER(PcgInfo), _vp]),
+    ("fe_vjp", _i32, [_vp, _vp, _vp, _vp, _vp]),
+    ("fe_newton", _i32, [_vp, ctypes.POINTER(_dbl), _i32, ctypes.POINTER(NewtonOpts), _vp, _vp,
+                         ctypes.POINTER(_dbl), ctypes.POINTER(NewtonInfo), _vp]),
+    ("fe_mean_stress", _i32, [_vp, _vp, _vp, ctypes.POINTER(_dbl), _vp]),
+    ("fe_read_flags", _i32, [_vp, ctypes.POINTER(_i32), _vp]),
+    ("fe_profile", _i32, [_vp, _i32]),
+    ("fe_profile_read", _i32, [_vp, ctypes.POINTER(_dbl)]),
+    ("fe_linearization_stats", _i32, [_vp, ctypes.POINTER(_i64), _vp]),
+    ("fe_status_string", ctypes.c_char_p, [_i32]),
+    ("fe_last_error", ctypes.c_char_p, []),
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} not found: build it with paper_2604_22087_amd/csrc/build.py")
+        lib = ctypes.CDLL(path)
+        for name, res, args in SIGNATURES:
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class FeError(RuntimeError):
+    def __init__(self, status, where):
+        lib = load_library()
+        msg = lib.fe_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({msg})")
+        self.status = status
+
+
+def _check(status, where):
+    if status != 0:
+        raise FeError(status, where)
+
+
+def _stream():
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return _vp(0) if t is None else _vp(t.data_ptr())
+
+
+@dataclass
+class PcgResult:
+    iterations: int
+    status: int
+    relres: float
+    bnorm: float
+
+
+class Problem:
+    """Structured n^3 hex8 RVE problem on the current GPU (precision 'f64' or 'f32')."""
+
+    def __init__(self, n: int, precision: str = "f64", device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the finite-element library runs on the GPU only")
+        self.lib = load_library()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.prec = F64 if precision == "f64" else F32
+        self.dtype = torch.float64 if self.prec == F64 else torch.float32
+        h = _vp()
+        with torch.cuda.device(self.device):
+            _check(self.lib.fe_problem_create(ctypes.byref(h), int(n), self.prec), "fe_problem_create")
+        self.handle = h
+        sz = (_i64 * 6)()
+        _check(self.lib.fe_problem_sizes(h, sz), "fe_problem_sizes")
+        self.n, self.n_el, self.n_nodes, self.n_dof, self.n_qp, self.nnz = (int(v) for v in sz)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.fe_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers -------------------------------------------------------------------
+    def _real(self, t, size, name):
+        if t is None:
+            return None
+        if t.device != self.device or t.dtype != self.dtype or not t.is_contiguous() or t.numel() != size:
+            raise ValueError(f"{name}: expected contiguous {self.dtype} tensor of {size} elements on {self.device}")
+        return t
+
+    def vector(self):
+        return torch.zeros(self.n_dof, dtype=self.dtype, device=self.device)
+
+    def state(self):
+        return torch.zeros(7 * 8 * self.n_el, dtype=self.dtype, device=self.device)
+
+    # -- setup ---------------------------------------------------------------------
+    def set_materials(self, phase, models, params, scale=None):
+        """phase: uint8 [n_el] (device); models: list of LINEAR/J2/NEOHOOKE;
+        params: list of (E, nu, sigma_y, H); scale: real [n_el] or None."""
+        if phase.dtype != torch.uint8 or phase.numel() != self.n_el or phase.device != self.device:
+            raise ValueError("phase must be a uint8 device tensor with one entry per element")
+        phase = phase.contiguous()
+        k = len(models)
+        m = (_i32 * k)(*models)
+        flat = [float(v) for row in params for v in (list(row) + [0.0] * (4 - len(row)))]
+        pr = (_dbl * (4 * k))(*flat)
+        self._real(scale, self.n_el, "scale")
+        _check(self.lib.fe_set_materials(self.handle, _ptr(phase), k, m, pr, _ptr(scale), _stream()),
+               "fe_set_materials")
+
+    def set_dirichlet(self, mask):
+        if mask is not None and (mask.dtype != torch.uint8 or mask.numel() != self.n_dof):
+            raise ValueError("mask must be uint8 with one entry per dof")
+        _check(self.lib.fe_set_dirichlet(self.handle, _ptr(mask), _stream()), "fe_set_dirichlet")
+
+    def lift(self, eps_bar, u, zero_free=False):
+        e = (_dbl * 9)(*[float(v) for v in torch.as_tensor(eps_bar, dtype=torch.float64).reshape(-1)])
+        self._real(u, self.n_dof, "u")
+        _check(self.lib.fe_lift(self.handle, e, _ptr(u), int(zero_free), _stream()), "fe_lift")
+        return u
+
+    # -- element operations ------------------------------------------------------------
+    def residual(self, u, state_in=None, state_out=None, r=None, apply_bc=False, store_tangent=False):
+        self._real(u, self.n_dof, "u")
+        self._real(state_in, 56 * self.n_el, "state_in")
+        self._real(state_out, 56 * self.n_el, "state_out")
+        r = self.vector() if r is None else self._real(r, self.n_dof, "r")
+        flags = (APPLY_BC if apply_bc else 0) | (STORE_TANGENT if store_tangent else 0)
+        _check(self.lib.fe_residual(self.handle, _ptr(u), _ptr(state_in), _ptr(state_out), _ptr(r), flags,
+                                    _stream()), "fe_residual")
+        return r
+
+    def csr_indices(self):
+        rp = torch.empty(self.n_dof + 1, dtype=torch.int32, device=self.device)
+        ci = torch.empty(self.nnz, dtype=torch.int32, device=self.device)
+        _check(self.lib.fe_csr_indices(self.handle, _ptr(rp), _ptr(ci), _stream()), "fe_csr_indices")
+        return rp, ci
+
+    def tangent_csr(self, u, state_in=None, vals=None, apply_bc=False):
+        self._real(u, self.n_dof, "u")
+        self._real(state_in, 56 * self.n_el, "state_in")
+        vals = torch.empty(self.nnz, dtype=self.dtype, device=self.device) if vals is None else \
+            self._real(vals, self.nnz, "vals")
+        _check(self.lib.fe_tangent_csr(self.handle, _ptr(u), _ptr(state_in), _ptr(vals), int(apply_bc),
+                                       _stream()), "fe_tangent_csr")
+        return vals
+
+    def apply_matfree(self, x, y=None, apply_bc=False):
+        self._real(x, self.n_dof, "x")
+        y = self.vector() if y is None else self._real(y, self.n_dof, "y")
+        _check(self.lib.fe_apply_matfree(self.handle, _ptr(x), _ptr(y), int(apply_bc), _stream()),
+               "fe_apply_matfree")
+        return y
+
+    def apply_csr(self, row_ptr, col_idx, vals, x, y=None):
+        self._real(x, self.n_dof, "x")
+        y = self.vector() if y is None else self._real(y, self.n_dof, "y")
+        _check(self.lib.fe_apply_csr(self.handle, _ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(x), _ptr(y),
+                                     _stream()), "fe_apply_csr")
+        return y
+
+    def diagonal(self, apply_bc=False, d=None):
+        d = self.vector() if d is None else self._real(d, self.n_dof, "d")
+        _check(self.lib.fe_diagonal(self.handle, _ptr(d), int(apply_bc), _stream()), "fe_diagonal")
+        return d
+
+    def pcg(self, b, x=None, op=OP_MATFREE, csr=None, rtol=1e-10, max_it=100000, check=True):
+        self._real(b, self.n_dof, "b")
+        x = self.vector() if x is None else self._real(x, self.n_dof, "x")
+        rp, ci, v = csr if csr is not None else (None, None, None)
+        info = PcgInfo()
+        st = self.lib.fe_pcg(self.handle, int(op), _ptr(rp), _ptr(ci), _ptr(v), _ptr(b), _ptr(x), float(rtol),
+                             int(max_it), ctypes.byref(info), _stream())
+        if check:
+            _check(st, "fe_pcg")
+        return x, PcgResult(info.iterations, info.status, info.relres, info.bnorm)
+
+    def vjp(self, u, lam, out=None):
+        self._real(u, self.n_dof, "u")
+        self._real(lam, self.n_dof, "lambda")
+        out = torch.empty(self.n_el, dtype=self.dtype, device=self.device) if out is None else \
+            self._real(out, self.n_el, "out")
+        _check(self.lib.fe_vjp(self.handle, _ptr(u), _ptr(lam), _ptr(out), _stream()), "fe_vjp")
+        return out
+
+    def newton(self, load_path, u=None, state=None, op=OP_MATFREE, max_newton=20, newton_rtol=1e-8,
+               pcg_rtol=1e-10, pcg_max_it=100000, assemble_csr=False, check=True):
+        """Load stepping; load_path: sequence of 3x3 macro strains. Returns (u, state, sigma_bar, info)."""
+        path = torch.as_tensor(np.asarray(load_path, dtype=np.float64)).reshape(-1, 9)
+        k = path.shape[0]
+        pa = (_dbl * (9 * k))(*path.reshape(-1).tolist())
+        u = self.vector() if u is None else self._real(u, self.n_dof, "u")
+        self._real(state, 56 * self.n_el, "state")
+        opts = NewtonOpts(int(op), int(bool(assemble_csr)), int(max_newton), float(newton_rtol), float(pcg_rtol),
+                          int(pcg_max_it))
+        sig = (_dbl * (6 * max(k, 1)))()
+        info = NewtonInfo()
+        st = self.lib.fe_newton(self.handle, pa, k, ctypes.byref(opts), _ptr(u), _ptr(state), sig,
+                                ctypes.byref(info), _stream())
+        if check:
+            _check(st, "fe_newton")
+        sb = [list(sig[6 * i:6 * i + 6]) for i in range(k)]
+        return u, state, sb, {f: getattr(info, f) for f, _ in NewtonInfo._fields_}
+
+    def mean_stress(self, u, state_in=None):
+        self._real(u, self.n_dof, "u")
+        out = (_dbl * 6)()
+        _check(self.lib.fe_mean_stress(self.handle, _ptr(u), _ptr(state_in), out, _stream()), "fe_mean_stress")
+        return list(out)
+
+    def read_flags(self):
+        f = _i32()
+        _check(self.lib.fe_read_flags(self.handle, ctypes.byref(f), _stream()), "fe_read_flags")
+        return f.value
+
+    # -- measurement -------------------------------------------------------------------
+    KERNEL_CLASSES = ("matfree_apply", "csr_spmv", "residual", "tangent_csr")
+
+    def profile(self, enable=True):
+        _check(self.lib.fe_profile(self.handle, int(enable)), "fe_profile")
+
+    def profile_read(self):
+        """{class: (launches, total_ms, algorithmic_bytes)} since profiling was enabled (synchronises)."""
+        out = (_dbl * 12)()
+        _check(self.lib.fe_profile_read(self.handle, out), "fe_profile_read")
+        return {k: (int(out[3 * i]), float(out[3 * i + 1]), float(out[3 * i + 2]))
+                for i, k in enumerate(self.KERNEL_CLASSES)}
+
+    def linearization_stats(self):
+        out = (_i64 * 2)()
+        _check(self.lib.fe_linearization_stats(self.handle, out, _stream()), "fe_linearization_stats")
+        return int(out[0]), int(out[1])

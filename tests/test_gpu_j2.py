@@ -1,0 +1,114 @@
+"""GPU parity of the J2 (radial return) path with the FP64 oracle: residual,
+trial state, consistent tangent as CSR and matrix-free operator, Newton load
+stepping on a fiber RVE.  Bars as in the linear tests; the number of Gauss
+points whose elastic/plastic branch differs is reported and must be 0 in FP64.
+"""
+import numpy as np
+import pytest
+
+from helpers import PHASES_J2_FIBER, lib_materials, oracle_phases, rel_err, state_from_lib, state_to_lib
+from oracle import assembly, solver
+from oracle.rve import RVE
+from paper_2604_22087_amd import inputs
+
+pytestmark = pytest.mark.gpu
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def _fiber_phase(n):
+    return inputs.fiber_phase(n, n_fibers=4, radius=0.18, seed=2)
+
+
+def _problem(n, prec, phase):
+    import torch
+    from paper_2604_22087_amd import fe
+    P = fe.Problem(n, prec)
+    models, params = lib_materials(PHASES_J2_FIBER)
+    P.set_materials(torch.tensor(phase, dtype=torch.uint8, device="cuda"), models, params)
+    return P
+
+
+def _t(P, a):
+    import torch
+    return torch.tensor(np.asarray(a), dtype=P.dtype, device="cuda")
+
+
+def _np(t):
+    return t.detach().double().cpu().numpy()
+
+
+def _plastic_state(rve, seed):
+    rng = np.random.default_rng(seed)
+    st = rve.zero_state()
+    ep = rng.normal(scale=2e-3, size=st["eps_p"].shape)
+    ep[..., 2] = -ep[..., 0] - ep[..., 1]
+    st["eps_p"] = ep * (rve.phase == 0)[:, None, None]
+    st["alpha"] = rng.uniform(0, 2e-3, st["alpha"].shape) * (rve.phase == 0)[:, None]
+    return st
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [6, 17])
+def test_j2_residual_state_tangent(n, prec):
+    import torch
+    print(f"[j2 parity] n={n} prec={prec}", flush=True)
+    phase = _fiber_phase(n)
+    rve = RVE(n, phase, oracle_phases(PHASES_J2_FIBER))
+    amp = 0.012 / n  # random gradients of ~1e-2 at every mesh size
+    u = rve.affine_lift(np.diag([0.03, -0.01, 0.0])) + inputs.random_displacement(n, -amp, amp, seed=7)
+    st = _plastic_state(rve, 11)
+    r_e, k_e, trial = rve.element_residual_tangent(u, st)
+    frac = trial["plastic"][rve.phase == 0].mean()
+    assert 0.2 < frac < 0.95
+    R = assembly.assemble_vector(rve.conn, r_e, rve.n_dof)
+    rp, ci, v = assembly.assemble_csr(rve.conn, k_e, rve.n_dof)
+
+    P = _problem(n, prec, phase)
+    tol = TOL[prec]
+    ut = _t(P, u)
+    s_in = _t(P, state_to_lib(st["eps_p"], st["alpha"]))
+    s_out = P.state()
+    r_g = P.residual(ut, s_in, s_out, store_tangent=True)
+    assert rel_err(_np(r_g), R) <= tol
+    ep_g, al_g = state_from_lib(_np(s_out), rve.conn.shape[0])
+    assert rel_err(ep_g, trial["eps_p"]) <= (1e-11 if prec == "f64" else 1e-4)
+    assert rel_err(al_g, trial["alpha"]) <= (1e-11 if prec == "f64" else 1e-4)
+    flips = int(np.sum((al_g > st["alpha"]) != trial["plastic"]))
+    print(f"  branch flips: {flips} of {trial['plastic'].size}", flush=True)
+    if prec == "f64":
+        assert flips == 0
+    x = np.random.default_rng(3).normal(size=rve.n_dof)
+    xt = _t(P, x)
+    assert rel_err(_np(P.apply_matfree(xt)), assembly.csr_matvec(rp, ci, v, x)) <= tol
+    assert rel_err(_np(P.diagonal()), solver.matfree_diagonal(rve.conn, k_e, rve.n_dof)) <= tol
+    v_g = P.tangent_csr(ut, s_in)
+    assert rel_err(_np(v_g), v) <= tol
+    mask = inputs.boundary_dof_mask(n)
+    P.set_dirichlet(torch.tensor(mask, device="cuda"))
+    assert rel_err(_np(P.apply_matfree(xt, apply_bc=True)), solver.matfree_apply(rve.conn, k_e, x, mask)) <= tol
+
+
+@pytest.mark.parametrize("op", ["matfree", "csr"])
+def test_j2_newton_ramp(op):
+    import torch
+    from paper_2604_22087_amd import fe
+    n = 6
+    print(f"[j2 newton] op={op}", flush=True)
+    phase = _fiber_phase(n)
+    rve = RVE(n, phase, oracle_phases(PHASES_J2_FIBER))
+    path = [np.diag([0.004 * k, 0.0, 0.0]) for k in range(1, 6)]
+    u_ref, st_ref, hist = rve.newton(path, newton_rtol=1e-11, pcg_rtol=1e-13)
+    assert hist[-1]["plastic_fraction"] > 0.2
+    P = _problem(n, "f64", phase)
+    P.set_dirichlet(torch.tensor(inputs.boundary_dof_mask(n), device="cuda"))
+    state = P.state()
+    u, state, sig, info = P.newton(path, state=state, op=fe.OP_MATFREE if op == "matfree" else fe.OP_CSR,
+                                   newton_rtol=1e-11, pcg_rtol=1e-13)
+    assert info["steps_done"] == len(path)
+    assert rel_err(_np(u), u_ref) <= 1e-8
+    ep_g, al_g = state_from_lib(_np(state), n ** 3)
+    assert rel_err(al_g, st_ref["alpha"]) <= 1e-7
+    for k, h in enumerate(hist):
+        assert rel_err(sig[k], h["sigma_bar"]) <= 1e-9
+    # iteration counts are reported, not pinned: rounding may move one iterate across the tolerance
+    assert abs(info["newton_iterations"] - sum(len(h["residuals"]) - 1 for h in hist)) <= len(path)

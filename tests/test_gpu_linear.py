@@ -1,0 +1,172 @@
+"""GPU parity of the linear-elastic path with the FP64 oracle (config: 8^3 sphere RVE
+and ragged brick counts), through the C ABI.
+
+Bars: CSR indices bit-exact; residual, CSR values, K*u (matrix-free and CSR),
+diagonal <= 1e-12 normwise relative in FP64 and <= 1e-5 in FP32; CG solutions
+<= 1e-8 relative when both sides solve to 1e-13.
+"""
+import numpy as np
+import pytest
+
+from helpers import PHASES_CONFIG1, lib_materials, oracle_phases, rel_err
+from oracle import assembly, solver
+from oracle.rve import RVE
+from paper_2604_22087_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def _problem(n, prec, phase, spec=PHASES_CONFIG1, scale=None):
+    import torch
+    from paper_2604_22087_amd import fe
+    P = fe.Problem(n, prec)
+    models, params = lib_materials(spec)
+    sc = None if scale is None else torch.tensor(scale, dtype=P.dtype, device="cuda")
+    P.set_materials(torch.tensor(phase, dtype=torch.uint8, device="cuda"), models, params, sc)
+    return P
+
+
+def _t(P, a):
+    import torch
+    return torch.tensor(np.asarray(a), dtype=P.dtype, device="cuda")
+
+
+def _np(t):
+    return t.detach().double().cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [8, 5, 17])
+def test_residual_tangent_operators(n, prec):
+    import torch
+    print(f"[linear parity] n={n} prec={prec}", flush=True)
+    phase = inputs.sphere_phase(n)
+    u = inputs.random_displacement(n, seed=1)
+    rve = RVE(n, phase, oracle_phases(PHASES_CONFIG1))
+    r_e, k_e, _ = rve.element_residual_tangent(u)
+    R = assembly.assemble_vector(rve.conn, r_e, rve.n_dof)
+    rp, ci, v = assembly.assemble_csr(rve.conn, k_e, rve.n_dof)
+
+    P = _problem(n, prec, phase)
+    ut = _t(P, u)
+    tol = TOL[prec]
+    assert rel_err(_np(P.residual(ut)), R) <= tol
+    rp_g, ci_g = P.csr_indices()
+    assert np.array_equal(rp_g.cpu().numpy().astype(np.int64), rp)
+    assert np.array_equal(ci_g.cpu().numpy().astype(np.int64), ci)
+    v_g = P.tangent_csr(ut)
+    assert rel_err(_np(v_g), v) <= tol
+    ku = assembly.csr_matvec(rp, ci, v, u)
+    assert rel_err(_np(P.apply_matfree(ut)), ku) <= tol
+    assert rel_err(_np(P.apply_csr(rp_g, ci_g, v_g, ut)), ku) <= tol
+    assert rel_err(_np(P.diagonal()), solver.matfree_diagonal(rve.conn, k_e, rve.n_dof)) <= tol
+
+    # Dirichlet-masked operators
+    mask = inputs.boundary_dof_mask(n)
+    P.set_dirichlet(torch.tensor(mask, device="cuda"))
+    x = np.random.default_rng(5).normal(size=rve.n_dof)
+    xt = _t(P, x)
+    y_ref = solver.matfree_apply(rve.conn, k_e, x, mask)
+    assert rel_err(_np(P.apply_matfree(xt, apply_bc=True)), y_ref) <= tol
+    vb = assembly.dirichlet_csr(rp, ci, v, mask)
+    vb_g = P.tangent_csr(ut, apply_bc=True)
+    assert rel_err(_np(vb_g), vb) <= tol
+    assert rel_err(_np(P.apply_csr(rp_g, ci_g, vb_g, xt)), y_ref) <= tol
+    assert rel_err(_np(P.diagonal(apply_bc=True)), solver.matfree_diagonal(rve.conn, k_e, rve.n_dof, mask)) <= tol
+    # residual with constrained entries zeroed
+    assert rel_err(_np(P.residual(ut, apply_bc=True)), R * (1 - mask)) <= tol
+
+
+@pytest.mark.parametrize("op", ["matfree", "csr"])
+def test_config1_solve_matches_oracle(op):
+    import torch
+    from paper_2604_22087_amd import fe
+    n = 8
+    print(f"[config1 solve] op={op}", flush=True)
+    phase = inputs.sphere_phase(n)
+    rve = RVE(n, phase, oracle_phases(PHASES_CONFIG1))
+    eb = np.diag([0.01, 0.0, 0.0])
+    u_ref, info = rve.solve_linear(eb, rtol=1e-13, op="csr")
+    r_e, k_e, _ = rve.element_residual_tangent(u_ref)
+    rp, ci, v = rve.bc_csr(k_e)
+
+    P = _problem(n, "f64", phase)
+    mask = torch.tensor(inputs.boundary_dof_mask(n), device="cuda")
+    P.set_dirichlet(mask)
+    u = P.vector()
+    P.lift(eb, u, zero_free=True)
+    b = P.residual(u, apply_bc=True)
+    b.neg_()
+    if op == "matfree":
+        w, res = P.pcg(b, op=fe.OP_MATFREE, rtol=1e-13, max_it=5000)
+    else:
+        rp_g, ci_g = P.csr_indices()
+        vb = P.tangent_csr(u, apply_bc=True)
+        w, res = P.pcg(b, op=fe.OP_CSR, csr=(rp_g, ci_g, vb), rtol=1e-13, max_it=5000)
+    assert res.status == 0 and res.relres <= 1e-13
+    assert abs(res.iterations - info["iterations"]) <= 3
+    u_g = _np(u + w)
+    assert rel_err(u_g, u_ref) <= 1e-8
+    # true residual of the GPU solution under the oracle's operator
+    rhs = -assembly.assemble_vector(rve.conn, rve.element_residual_tangent(rve.affine_lift(eb))[0], rve.n_dof) * rve.free
+    w_g = u_g - rve.affine_lift(eb)
+    assert np.linalg.norm(rhs - assembly.csr_matvec(rp, ci, v, w_g)) <= 1e-12 * np.linalg.norm(rhs)
+    # single linear load step through the Newton driver
+    u2, _, sig, ninfo = P.newton([eb], op=fe.OP_MATFREE if op == "matfree" else fe.OP_CSR, pcg_rtol=1e-13,
+                                 newton_rtol=1e-10)
+    assert ninfo["steps_done"] == 1
+    assert rel_err(_np(u2), u_ref) <= 1e-8
+    sbar = rve.mean_stress(rve.element_residual_tangent(u_ref)[2]["sigma_all"])
+    assert rel_err(sig[0], sbar) <= 1e-8
+
+
+def test_scale_field_and_vjp():
+    """Per-element modulus scale; vjp_e = lambda_e . K_hat_e u_e against the oracle."""
+    n = 6
+    phase = np.zeros(n ** 3, dtype=np.uint8)
+    scale = inputs.uniform_field(n ** 3, 1.0, 10.0, seed=4)
+    spec = [("linear", 1.0, 0.3)]
+    u = inputs.random_displacement(n, seed=2)
+    lam_vec = inputs.random_displacement(n, seed=3)
+    rve = RVE(n, phase, oracle_phases(spec), scale=scale)
+    r_e, k_e, _ = rve.element_residual_tangent(u)
+    R = assembly.assemble_vector(rve.conn, r_e, rve.n_dof)
+    ref_hat = RVE(n, phase, oracle_phases(spec))
+    r_hat, _, _ = ref_hat.element_residual_tangent(u)
+    from oracle.mesh import element_dofs
+    vjp_ref = np.einsum("ei,ei->e", lam_vec[element_dofs(rve.conn)], r_hat)
+    P = _problem(n, "f64", phase, spec, scale)
+    assert rel_err(_np(P.residual(_t(P, u))), R) <= 1e-12
+    assert rel_err(_np(P.vjp(_t(P, u), _t(P, lam_vec))), vjp_ref) <= 1e-12
+
+
+def test_error_paths_from_host():
+    """Forced failures: non-SPD operator, non-finite rhs, iteration limit, missing linearisation."""
+    import torch
+    from paper_2604_22087_amd import fe
+    n = 4
+    phase = np.zeros(n ** 3, dtype=np.uint8)
+    P = _problem(n, "f64", phase, [("linear", -1.0, 0.3)])
+    P.set_dirichlet(torch.tensor(inputs.boundary_dof_mask(n), device="cuda"))
+    b = P.vector()
+    b[3 * 31] = 1.0  # an interior dof (node 31 = (1,1,1) in the 5^3 node grid)
+    _, res = P.pcg(b, op=fe.OP_MATFREE, rtol=1e-10, max_it=100, check=False)
+    assert res.status == 5  # breakdown
+    P2 = _problem(n, "f64", phase, [("linear", 1.0, 0.3)])
+    P2.set_dirichlet(torch.tensor(inputs.boundary_dof_mask(n), device="cuda"))
+    bn = P2.vector()
+    bn[3 * 31] = float("nan")
+    _, res = P2.pcg(bn, rtol=1e-10, max_it=100, check=False)
+    assert res.status == 6
+    b2 = P2.vector()
+    b2[3 * 31] = 1.0
+    _, res = P2.pcg(b2, rtol=1e-14, max_it=1, check=False)
+    assert res.status == 4 and res.iterations == 1
+    P3 = _problem(n, "f64", phase, [("j2", 3.5, 0.35, 0.05, 0.1)])
+    with pytest.raises(fe.FeError) as ei:
+        P3.apply_matfree(P3.vector())
+    assert ei.value.status == 8
+    with pytest.raises(fe.FeError):
+        P3.vjp(P3.vector(), P3.vector())
