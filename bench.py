@@ -52,11 +52,14 @@ def setup(n, prec):
 
 
 def run_ramp(P, u, state, path):
+    """Newton tolerances: 1e-8 / 1e-10 in FP64; FP32 residuals carry rounding noise near 1e-7
+    relative, so the FP32 run stops at 1e-5 / 1e-6 and its error against FP64 is reported."""
     from paper_2604_22087_amd import fe
     u.zero_()
     state.zero_()
-    return P.newton(path, u=u, state=state, op=fe.OP_MATFREE, assemble_csr=True, newton_rtol=1e-8,
-                    pcg_rtol=1e-10, max_newton=20)
+    f64 = P.prec == fe.F64
+    return P.newton(path, u=u, state=state, op=fe.OP_MATFREE, assemble_csr=True,
+                    newton_rtol=1e-8 if f64 else 1e-5, pcg_rtol=1e-10 if f64 else 1e-6, max_newton=30)
 
 
 def cpu_baseline(n, phase, gpu_info, path):

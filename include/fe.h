@@ -88,6 +88,7 @@ typedef struct {
   int pcg_iterations;    /* summed over all linear solves */
   int operator_applies;  /* K*x applications (one per CG iteration plus one per solve) */
   int steps_done;        /* load steps that converged */
+  int line_search_halvings; /* step halvings taken by the line search, summed */
   int status;            /* fe_status of the whole run */
   double last_residual;  /* ||P_f R|| at the end of the last step */
 } fe_newton_info;
@@ -168,7 +169,9 @@ int fe_vjp(fe_problem* p, const void* u, const void* lambda, void* out, void* st
 
 /* Newton load stepping: for each of n_steps macro strains (load_path_host:
  * [n_steps][3][3] row-major) lift the boundary, iterate Newton with the chosen
- * operator until the opts tolerance, then commit the plastic state.
+ * operator until the opts tolerance, then commit the plastic state.  Each
+ * Newton update w is taken as u += s w with s = 1 halved (at most 5 times)
+ * while ||P_f R(u + s w)|| >= ||P_f R(u)||.
  * u: real [n_dof] in/out (the starting field); state: real [7][8][n_el] in/out
  * (NULL for problems without J2 phases); sigma_bar_host: [n_steps][6] volume
  * averaged stress after each step, or NULL. */

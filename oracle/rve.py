@@ -11,13 +11,17 @@ Readings where the paper is silent:
   * Newton per load step: predictor moves only the boundary values; stop when
     ||P_f R|| <= newton_rtol * ||P_f R||_first (or it is exactly 0), at most
     max_newton iterations; the plastic state is committed on convergence and
-    every evaluation starts from the last committed state.
+    every evaluation starts from the last committed state;
+  * globalisation: the step u + s w starts at s = 1 and is halved while
+    ||P_f R(u + s w)|| >= ||P_f R(u)||, at most max_halvings times (the last
+    trial is taken).  Full steps cycle when many ligament points switch between
+    elastic and plastic; the halving line search is the textbook remedy.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import assembly, element, j2, solver
+from . import assembly, element, j2, neohooke, solver
 from .elasticity import lame
 from .hex8 import gauss_points, physical_gradients
 from .mesh import boundary_nodes, structured_hex8
@@ -90,6 +94,21 @@ class RVE:
                      sigma_all=np.zeros((ne, 8, 6)))
         r_e, k_e = element.residual_and_tangent(self.coords, self.conn, u,
                                                 self._material(state_n, trial), want_tangent)
+        nh_ids = [pid for pid, p in enumerate(self.phases) if p["model"] == "neohooke"]
+        if nh_ids:  # finite-strain phases replace their small-strain evaluation
+            sel = np.isin(self.phase, nh_ids)
+            mu_e, lam_e = np.zeros(ne), np.zeros(ne)
+            for pid in nh_ids:
+                lam, mu = lame(self.phases[pid]["E"], self.phases[pid]["nu"])
+                s = self.phase == pid
+                lam_e[s], mu_e[s] = lam * self.scale[s], mu * self.scale[s]
+            r_n, k_n, p_qp = neohooke.residual_tangent(self.coords, self.conn[sel], u, mu_e[sel], lam_e[sel],
+                                                       want_tangent)
+            r_e[sel] = r_n
+            if want_tangent:
+                k_e[sel] = k_n
+            trial["sigma_all"][sel] = np.stack([p_qp[..., 0, 0], p_qp[..., 1, 1], p_qp[..., 2, 2],
+                                                p_qp[..., 1, 2], p_qp[..., 0, 2], p_qp[..., 0, 1]], axis=-1)
         return r_e, k_e, trial
 
     def residual(self, u, state_n=None):
@@ -127,20 +146,23 @@ class RVE:
         return u + w, dict(iterations=it, status=status, true_relres=rel)
 
     def newton(self, load_path, newton_rtol=1e-8, max_newton=20, pcg_rtol=1e-10,
-               pcg_max_it=20000, op="csr"):
+               pcg_max_it=20000, op="csr", max_halvings=5):
         """Load stepping: for each macro strain in load_path, Newton to tolerance."""
         u = np.zeros(self.n_dof)
         state = self.zero_state()
         history = []
+
+        def evaluate(v):
+            r_e, k_e, trial = self.element_residual_tangent(v, state)
+            rf = assembly.assemble_vector(self.conn, r_e, self.n_dof) * self.free
+            return rf, np.linalg.norm(rf), k_e, trial
+
         for eps_bar in load_path:
             u = u * self.free + self.affine_lift(eps_bar)
-            rec = dict(eps_bar=np.asarray(eps_bar), residuals=[], pcg_iterations=[])
-            r0 = None
+            rec = dict(eps_bar=np.asarray(eps_bar), residuals=[], pcg_iterations=[], steps=[])
+            rf, rn, k_e, trial = evaluate(u)
+            r0 = rn
             for it in range(max_newton + 1):
-                r_e, k_e, trial = self.element_residual_tangent(u, state)
-                rf = assembly.assemble_vector(self.conn, r_e, self.n_dof) * self.free
-                rn = np.linalg.norm(rf)
-                r0 = rn if r0 is None else r0
                 rec["residuals"].append(rn)
                 if rn <= newton_rtol * r0 or rn == 0.0:
                     break
@@ -150,7 +172,15 @@ class RVE:
                 if status != solver.OK:
                     raise RuntimeError(f"PCG failed: {status}")
                 rec["pcg_iterations"].append(pit)
-                u = u + w
+                s = 1.0
+                for halving in range(max_halvings + 1):
+                    trial_eval = evaluate(u + s * w)
+                    if trial_eval[1] < rn or halving == max_halvings:
+                        break
+                    s *= 0.5
+                rec["steps"].append(s)
+                u = u + s * w
+                rf, rn, k_e, trial = trial_eval
             state = dict(eps_p=trial["eps_p"], alpha=trial["alpha"])
             rec["sigma_bar"] = self.mean_stress(trial["sigma_all"])
             rec["plastic_fraction"] = float(np.mean(trial["plastic"]))

@@ -530,26 +530,33 @@ extern "C" int fe_newton(fe_problem* p, const double* path, int n_steps, const f
   void* r = p->w_v;
   void* w = p->w_v2;
   void* trial = p->model_set == MS_J2 ? p->w_state : nullptr;
+  // residual, its norm and the linearisation at u (state: last committed)
+  auto evaluate = [&](double* norm) -> int {
+    int st = residual_impl(p, u, state, trial, r, FE_APPLY_BC | FE_STORE_TANGENT, nullptr, s);
+    if (st) return st;
+    if ((st = read_norm(p, r, s, norm))) return st;
+    int fl = 0;
+    if ((st = fe_read_flags(p, &fl, stream))) return st;
+    if (fl & 1) {
+      set_error("inverted element");
+      return FE_ERR_INVERTED;
+    }
+    if (!std::isfinite(*norm)) {
+      set_error("non-finite residual");
+      return FE_ERR_NONFINITE;
+    }
+    return FE_OK;
+  };
+  const int max_halvings = 5;
   for (int step = 0; step < n_steps; ++step) {
     HIPCHK(launch_lift(p, path + 9 * step, u, 0, s));
     double r0 = -1.0, rn = 0.0;
     bool converged = false;
-    for (int it = 0; it <= o->max_newton; ++it) {
-      int st = residual_impl(p, u, state, trial, r, FE_APPLY_BC | FE_STORE_TANGENT, nullptr, s);
-      if (st) return st;
-      if ((st = read_norm(p, r, s, &rn))) return st;
-      int fl = 0;
-      if ((st = fe_read_flags(p, &fl, stream))) return st;
-      if (fl & 1) {
-        set_error("inverted element");
-        inf.status = FE_ERR_INVERTED;
-        break;
-      }
-      if (!std::isfinite(rn)) {
-        set_error("non-finite residual");
-        inf.status = FE_ERR_NONFINITE;
-        break;
-      }
+    int est = evaluate(&rn);
+    if (est == FE_ERR_HIP || est == FE_ERR_OOM) return est;
+    if (est) inf.status = est;
+    for (int it = 0; inf.status == FE_OK && it <= o->max_newton; ++it) {
+      int st = FE_OK;
       if (r0 < 0) r0 = rn;
       if (rn <= o->newton_rtol * r0 || rn == 0.0) {
         converged = true;
@@ -573,7 +580,22 @@ extern "C" int fe_newton(fe_problem* p, const double* path, int n_steps, const f
         inf.status = st;
         break;
       }
-      HIPCHK(launch_axpby(p, p->n_dof, 1.0, w, 1.0, u, s));
+      // halving line search on ||P_f R||: u += s w with s = 1, 1/2, ... while the norm does not drop
+      const double r_prev = rn;
+      double sc = 1.0;
+      HIPCHK(launch_axpby(p, p->n_dof, sc, w, 1.0, u, s));
+      for (int hv = 0;; ++hv) {
+        st = evaluate(&rn);
+        if (st == FE_ERR_HIP || st == FE_ERR_OOM) return st;
+        if ((st == FE_OK && rn < r_prev) || hv == max_halvings) break;
+        HIPCHK(launch_axpby(p, p->n_dof, -0.5 * sc, w, 1.0, u, s));  // back to u_old + (sc/2) w
+        sc *= 0.5;
+      }
+      inf.line_search_halvings += (int)std::lround(-std::log2(sc));
+      if (st) {
+        inf.status = st;
+        break;
+      }
     }
     inf.last_residual = rn;
     if (inf.status != FE_OK) break;

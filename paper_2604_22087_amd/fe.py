@@ -40,7 +40,7 @@ class NewtonOpts(ctypes.Structure):
 
 class NewtonInfo(ctypes.Structure):
     _fields_ = [("newton_iterations", _i32), ("pcg_iterations", _i32), ("operator_applies", _i32),
-                ("steps_done", _i32), ("status", _i32), ("last_residual", _dbl)]
+                ("steps_done", _i32), ("line_search_halvings", _i32), ("status", _i32), ("last_residual", _dbl)]
 
 
 # (name, restype, argtypes) of every exported entry point

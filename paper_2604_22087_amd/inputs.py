@@ -116,6 +116,17 @@ def boundary_dof_mask(n: int) -> np.ndarray:
     return np.repeat(node, 3)
 
 
+def glorot_uniform_params(layers=(13, 128, 128, 128, 6), seed: int = 5):
+    """Initial MLP weights: W_l (out, in) ~ U(-a, a), a = sqrt(6 / (in + out)), b_l = 0,
+    drawn layer by layer from default_rng(seed).  Returns a list of (W, b) float64 arrays."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for fan_in, fan_out in zip(layers[:-1], layers[1:]):
+        a = np.sqrt(6.0 / (fan_in + fan_out))
+        params.append((rng.uniform(-a, a, (fan_out, fan_in)), np.zeros(fan_out)))
+    return params
+
+
 def fd_element_picks(n_el: int, count: int = 64, seed: int = 40) -> np.ndarray:
     """Element ids for the finite-difference gradient check."""
     return np.sort(np.random.default_rng(seed).choice(n_el, count, replace=False))

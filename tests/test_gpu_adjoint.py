@@ -1,0 +1,86 @@
+"""GPU adjoint gradient (config: linear RVE with E_e ~ U(1,10), compliance under
+macro strain 0.01) against the FP64 oracle and central finite differences.
+
+Bars: objective and gradient <= 1e-10 normwise against the oracle's own solve
+(small mesh); at 64^3 the per-element gradient at the GPU solution matches the
+oracle element by element (<= 1e-12), Euler's identity sum E_e dJ/dE_e = J holds
+(<= 1e-10), and central differences with h = 1e-6 on 64 seeded elements agree
+(<= 1e-4 relative; the objective is summed exactly from non-negative element
+energies so rounding stays far below the 2e-12 relative change the step makes).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from helpers import rel_err
+from oracle import adjoint as oadj
+from oracle.rve import RVE, phase_params
+from paper_2604_22087_amd import inputs
+
+pytestmark = pytest.mark.gpu
+EB = np.diag([0.01, 0.0, 0.0])
+
+
+def _torch_setup(n, E):
+    import torch
+    from paper_2604_22087_amd import fe
+    P = fe.Problem(n, "f64")
+    phase = torch.zeros(n ** 3, dtype=torch.uint8, device="cuda")
+    mask = torch.tensor(inputs.boundary_dof_mask(n), device="cuda")
+    Et = torch.tensor(E, device="cuda", requires_grad=True)
+    return P, phase, mask, Et
+
+
+def test_adjoint_gradient_matches_oracle_small():
+    from paper_2604_22087_amd.adjoint import compliance
+    n = 6
+    E = inputs.uniform_field(n ** 3, 1.0, 10.0, seed=4)
+    rve = RVE(n, np.zeros(n ** 3, dtype=int), [phase_params("linear", 1.0, 0.3)], scale=E)
+    u_ref, _ = rve.solve_linear(EB, rtol=1e-14)
+    g_ref, lam_ref = oadj.gradient(rve, u_ref)
+    J_ref = oadj.reaction_objective(rve, u_ref)
+    P, phase, mask, Et = _torch_setup(n, E)
+    J = compliance(Et, P, phase, mask, EB, rtol=1e-13)
+    J.backward()
+    assert float(J) == pytest.approx(J_ref, rel=1e-10)
+    assert rel_err(Et.grad.cpu().numpy(), g_ref) <= 1e-10
+
+
+def test_adjoint_fullsize_fd_and_euler():
+    import torch
+    from paper_2604_22087_amd.adjoint import compliance
+    n = 64
+    E = inputs.uniform_field(n ** 3, 1.0, 10.0, seed=4)
+    P, phase, mask, Et = _torch_setup(n, E)
+    J = compliance(Et, P, phase, mask, EB, rtol=1e-13)
+    J.backward()
+    g = Et.grad.double().cpu().numpy()
+    print(f"[adjoint 64^3] J={float(J):.10e}", flush=True)
+    assert np.all(g > 0)
+    assert float(np.dot(E, g)) == pytest.approx(float(J), rel=1e-10)
+    # element-level parity of dJ/dE_e at the GPU solution (oracle evaluates sampled elements)
+    from paper_2604_22087_amd import fe
+    u = P.newton([EB], op=fe.OP_MATFREE, pcg_rtol=1e-13, newton_rtol=1e-12)[0]
+    picks = inputs.fd_element_picks(n ** 3, 64, seed=40)
+    sub = RVE(n, np.zeros(n ** 3, dtype=int), [phase_params("linear", 1.0, 0.3)], scale=E, elements=picks)
+    un = u.double().cpu().numpy()
+    assert rel_err(g[picks], oadj.vjp_scale(sub, un, un)) <= 1e-12
+
+    def energy(Evec):
+        P.set_materials(phase, [fe.LINEAR], [(1.0, 0.3)], torch.tensor(Evec, device="cuda"))
+        uu = P.newton([EB], op=fe.OP_MATFREE, pcg_rtol=1e-13, newton_rtol=1e-12)[0]
+        e_el = (torch.tensor(Evec, device="cuda") * P.vjp(uu, uu)).double().cpu().numpy()
+        return math.fsum(e_el.tolist())
+
+    h = 1e-6
+    errs = []
+    for k in picks:
+        Ep, Em = E.copy(), E.copy()
+        Ep[k] += h
+        Em[k] -= h
+        fd = (energy(Ep) - energy(Em)) / (2 * h)
+        errs.append(abs(fd - g[k]) / abs(g[k]))
+    errs = np.array(errs)
+    print(f"  FD vs adjoint on 64 elements: median {np.median(errs):.2e} max {errs.max():.2e}", flush=True)
+    assert errs.max() <= 1e-4
