@@ -207,6 +207,29 @@ int fe_linearization_stats(fe_problem* p, int64_t* out_host, void* stream);
  * (bit 0: inverted element).  Synchronises and clears. */
 int fe_read_flags(fe_problem* p, int* flags_host, void* stream);
 
+/* ---- learned constitutive surrogate (Sec. III-B: a surrogate may replace the
+ * designed stress-strain function, its Jacobian serving as the tangent) ----
+ * Network: dense 13 -> 128 -> 128 -> 128 -> 6, SiLU after the hidden layers,
+ * linear output.  Parameters are FP32 on the device, FE_MLP_PARAMS floats: for
+ * layers l = 1..4 in order, the weights input-major Wt_l[in][out] followed by
+ * the bias b_l[out].  Inputs/outputs are the normalised quantities. */
+enum { FE_MLP_IN = 13, FE_MLP_HIDDEN = 128, FE_MLP_OUT = 6, FE_MLP_PARAMS = 35590 };
+
+/* y = net(x): x float [n][13], y float [n][6].  jac (float [n][6][6], may be
+ * NULL): jac[s][o][j] = dy_o/dx_j for the first six inputs (forward-mode
+ * tangents carried through FP32 matrix cores).  cache (float [n][3][128], may
+ * be NULL): hidden pre-activations, for fe_mlp_backward. */
+int fe_mlp_forward(const float* W, const float* x, float* y, float* jac, float* cache, int64_t n, void* stream);
+
+/* Gradients of L = mean_s sum_o (y - target)^2 over the n samples of one batch:
+ * dW (float [FE_MLP_PARAMS]) is overwritten; loss_dev (double [1]) receives L. */
+int fe_mlp_backward(const float* W, const float* x, const float* cache, const float* y, const float* target,
+                    float* dW, double* loss_dev, int64_t n, void* stream);
+
+/* One Adam step (Kingma & Ba), t >= 1: m, v are the first/second moment buffers. */
+int fe_adam_step(float* W, const float* dW, float* m, float* v, int64_t n_param, double lr, double beta1,
+                 double beta2, double eps, int t, void* stream);
+
 const char* fe_status_string(int status);
 const char* fe_last_error(void);
 

@@ -1,6 +1,7 @@
 // Host side of libfe: the extern "C" entry points declared in include/fe.h.
 // Argument checks happen before anything is enqueued; HIP failures become
 // FE_ERR_HIP with the runtime's message kept in a thread-local string.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -117,6 +118,7 @@ void fe_problem_destroy(fe_problem* p) {
   free_dev(p->u_lin);
   free_dev(p->w_r);
   free_dev(p->w_p);
+  free_dev(p->w_p2);
   free_dev(p->w_q);
   free_dev(p->w_d);
   free_dev(p->w_v);
@@ -155,9 +157,10 @@ int fe_problem_create(fe_problem** out, int n, int precision) {
   HIPCHK(hipGetDevice(&p->device));
   const size_t rs = real_size(p), vec = rs * p->n_dof;
   int st = FE_OK;
+  const size_t n_part = std::max<size_t>(2 * 1024, (size_t)elem_grid_size(n));
   if ((st = alloc((void**)&p->phase, p->n_el)) || (st = alloc(&p->w_r, vec)) || (st = alloc(&p->w_p, vec)) ||
-      (st = alloc(&p->w_q, vec)) || (st = alloc(&p->w_d, vec)) ||
-      (st = alloc((void**)&p->partials, 2 * 1024 * sizeof(double))) ||
+      (st = alloc(&p->w_p2, vec)) || (st = alloc(&p->w_q, vec)) || (st = alloc(&p->w_d, vec)) ||
+      (st = alloc((void**)&p->partials, n_part * sizeof(double))) ||
       (st = alloc((void**)&p->counter, sizeof(unsigned int))) || (st = alloc((void**)&p->ctrl, sizeof(CgCtrl))) ||
       (st = alloc((void**)&p->stress_sum, 8 * sizeof(double))) || (st = alloc((void**)&p->flags, sizeof(int)))) {
     fe_problem_destroy(p);
@@ -424,10 +427,11 @@ static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, 
   const size_t rec0 = p->prof_recs.size();
   const int cls = op == FE_OP_CSR ? 1 : 0;
   int launched = 0, chunk = 8;
+  long k = 0;
   for (;;) {
-    for (int k = 0; k < chunk; ++k) {
-      PROF(p, s, cls, cg_operator(p, op, rp, ci, vals, s));
-      HIPCHK(cg_vectors(p, x, s));
+    for (int c = 0; c < chunk; ++c, ++k) {
+      PROF(p, s, cls, cg_operator(p, op, rp, ci, vals, k, s));
+      HIPCHK(cg_vectors(p, op, x, k, s));
     }
     launched += chunk;
     HIPCHK(hipMemcpyAsync(p->host_ctrl, p->ctrl, sizeof(CgCtrl), hipMemcpyDeviceToHost, s));
@@ -443,6 +447,8 @@ static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, 
     if (p->prof_recs.size() > rec0 + executed) p->prof_recs.resize(rec0 + executed);
     double b = 0;
     if (int e = operator_bytes(p, op, s, &b)) return e;
+    // the fused matrix-free CG operator reads r, M^-1, p_old and writes p instead of reading x
+    if (op == FE_OP_MATFREE) b += 3.0 * (double)real_size(p) * (double)p->n_dof;
     p->prof_bytes[cls] += b * (double)executed;
   }
   if (info) {

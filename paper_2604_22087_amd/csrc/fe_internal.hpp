@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <string>
 #include <utility>
@@ -32,7 +34,8 @@ enum ModelSet { MS_LINEAR = 0, MS_J2 = 1, MS_NH = 2 };
 enum ElemOp {
   OP_RESID = 0,   // r = sum_e A_e^T r_e(u)        (+ state / linearisation side outputs)
   OP_APPLY = 1,   // y = K_lin x                   (matrix-free)
-  OP_VJP = 2      // out_e = lambda_e . d r_e / d s_e
+  OP_VJP = 2,     // out_e = lambda_e . d r_e / d s_e
+  OP_CG_APPLY = 3 // CG: p = M^-1 r + beta p_old (written by the owning brick), q = A p, p.Ap -> alpha
 };
 
 // CG status word: kernels stop on any non-zero value, so "converged" must differ from 0.
@@ -72,6 +75,14 @@ struct ElemArgs {
   int apply_bc;
   int store_tangent;
   Phases mat;
+  // OP_CG_APPLY only
+  const void* cg_r;       // residual r
+  const void* cg_dinv;    // inverse Jacobi diagonal
+  const void* cg_pold;    // previous search direction
+  void* cg_pnew;          // new search direction (written)
+  CgCtrl* ctrl;
+  double* partials;
+  unsigned int* counter;
 };
 
 template <typename T> struct Buf { T* p = nullptr; };
@@ -96,6 +107,7 @@ struct fe_problem {
   // solver workspace
   void* w_r = nullptr;
   void* w_p = nullptr;
+  void* w_p2 = nullptr;       // second search-direction buffer (fused matrix-free CG)
   void* w_q = nullptr;
   void* w_d = nullptr;        // inverse diagonal
   void* w_v = nullptr;        // scratch vector (Newton)
@@ -147,8 +159,10 @@ hipError_t launch_lin_stats(const fe_problem* p, unsigned long long* out, hipStr
 
 // CG pieces: one iteration = cg_operator (q = A p) then cg_vectors (scalars and updates)
 hipError_t cg_init(const fe_problem* p, const void* b, void* x, double rtol, int max_it, hipStream_t s);
-hipError_t cg_operator(const fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals,
+// (matrix-free: one fused element launch that also forms p and p.Ap, then one update launch)
+hipError_t cg_operator(const fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, long k,
                        hipStream_t s);
-hipError_t cg_vectors(const fe_problem* p, void* x, hipStream_t s);
+hipError_t cg_vectors(const fe_problem* p, int op, void* x, long k, hipStream_t s);
+int elem_grid_size(int n);  // workgroups of an element-kernel launch (also the partial-sum slots it needs)
 
 }  // namespace fe

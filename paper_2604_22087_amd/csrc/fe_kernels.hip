@@ -38,6 +38,65 @@ constexpr int VGRID_MAX = 1024; // vector kernels: blocks (== partial-sum slots)
 
 template <typename T> __device__ __forceinline__ void atomic_add(T* p, T v) { unsafeAtomicAdd(p, v); }
 
+// Block sum of a double over 256 lanes; the result is valid in lane 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < VBLOCK / 64; ++i) r += sh[i];
+  return r;
+}
+
+// Last-block-done: every block publishes partials, the last one to arrive
+// reduces them in block order (deterministic) and resets the counter.
+__device__ __forceinline__ bool arrive_last(unsigned int* counter) {
+  __shared__ bool last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (last) __threadfence();
+  return last;
+}
+
+__device__ __forceinline__ double load_coherent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum of partials[0..nb) in fixed order by the whole block; valid in lane 0.
+__device__ __forceinline__ double reduce_partials(const double* partials, int nb, double* sh) {
+  double v = 0;
+  for (int i = threadIdx.x; i < nb; i += VBLOCK) v += load_coherent(partials + i);
+  return block_sum(v, sh);
+}
+
+__device__ __forceinline__ bool finite(double v) { return v == v && v - v == 0.0; }
+
+// CG step length from the block partials of p.Ap (last block): alpha = rz / pAp.
+__device__ __forceinline__ void cg_alpha_arrive(double v, CgCtrl* ctrl, double* partials, unsigned int* counter,
+                                                double* sh) {
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+  if (arrive_last(counter)) {
+    const double pq = reduce_partials(partials, gridDim.x, sh);
+    if (threadIdx.x == 0) {
+      ctrl->pq = pq;
+      if (!finite(pq))
+        ctrl->status = FE_ERR_NONFINITE;
+      else if (pq <= 0.0)
+        ctrl->status = FE_ERR_BREAKDOWN;
+      else
+        ctrl->alpha = ctrl->rz / pq;
+      *counter = 0;
+    }
+  }
+}
+
 // G[r][q] = sum_{k,j} M[r][k] M[q][j] D[k][j] with M = [[GA,GB],[GB,GA]] (M symmetric,
 // so the same map also pushes Gauss-point values back to the nodes).
 template <typename T> __device__ __forceinline__ void interp2(const T D[2][2], T G[2][2]) {
@@ -322,7 +381,8 @@ __device__ __forceinline__ void nh_apply(const T dH[3][3], const T FiT[3][3], T 
 
 template <typename T, int OP, int MS>
 __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* stop) {
-  constexpr bool NEED_L = (OP == OP_VJP) || (OP == OP_APPLY && MS == MS_NH);
+  constexpr bool APPLY_LIKE = (OP == OP_APPLY) || (OP == OP_CG_APPLY);
+  constexpr bool NEED_L = (OP == OP_VJP) || (APPLY_LIKE && MS == MS_NH);
   __shared__ T s_x[NN * 3];
   __shared__ T s_y[OP == OP_VJP ? 1 : NN * 3];
   __shared__ T s_l[NEED_L ? NN * 3 : 1];
@@ -334,11 +394,20 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
   const int nb = ntx * nty * ntz;
   const int per = (nb + 7) >> 3;
   const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  if (tile >= nb) return;
+  if (tile >= nb) {
+    // padding block of the XCD-aware numbering: still takes part in the p.Ap reduction
+    if (OP == OP_CG_APPLY) cg_alpha_arrive(0.0, a.ctrl, a.partials, a.counter, &s_red[0][0]);
+    return;
+  }
   const int a0 = (tile % ntx) * TX, b0 = ((tile / ntx) % nty) * TY, c0 = (tile / (ntx * nty)) * TZ;
   const int tid = threadIdx.x;
   const T* X = static_cast<const T*>(a.x);
   const T* XL = static_cast<const T*>(a.xlin);
+  const T* CR = static_cast<const T*>(a.cg_r);
+  const T* CD = static_cast<const T*>(a.cg_dinv);
+  const T* CP = static_cast<const T*>(a.cg_pold);
+  T* CPN = static_cast<T*>(a.cg_pnew);
+  const T cg_beta = (OP == OP_CG_APPLY) ? T(a.ctrl->beta) : T(0);
   const int64_t np1 = n + 1;
 
   for (int i = tid; i < NN * 3; i += EBLOCK) {
@@ -348,8 +417,14 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
     T v = 0, vl = 0;
     if (gi <= n && gj <= n && gk <= n) {
       const int64_t dof = 3 * (gi + np1 * (gj + np1 * gk)) + c;
-      v = X[dof];
-      if (OP == OP_APPLY && a.apply_bc && a.mask && a.mask[dof]) v = 0;
+      if (OP == OP_CG_APPLY) {
+        // new search direction, formed identically by every brick that touches the node
+        v = CD[dof] * CR[dof] + cg_beta * CP[dof];
+        if ((min(gi, n - 1) - a0 < TX) && (min(gj, n - 1) - b0 < TY) && (min(gk, n - 1) - c0 < TZ)) CPN[dof] = v;
+      } else {
+        v = X[dof];
+      }
+      if (APPLY_LIKE && a.apply_bc && a.mask && a.mask[dof]) v = 0;
       if (NEED_L) vl = XL[dof];
     }
     s_x[i] = v;
@@ -397,7 +472,7 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
 
     // Neo-Hookean APPLY also needs the gradient at the linearisation point
     T Lx[2][2][3], Ly[2][2][3], Lz[2][2][3];
-    if (OP == OP_APPLY && MS == MS_NH) {
+    if (APPLY_LIKE && MS == MS_NH) {
 #pragma unroll
       for (int k = 0; k < 2; ++k)
 #pragma unroll
@@ -454,7 +529,7 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
                 for (int k = 0; k < 6; ++k) tang[(int64_t)(k * 8 + qp) * ne + e] = tn[k];
               }
               done = true;
-            } else if (OP == OP_APPLY) {
+            } else if (APPLY_LIKE) {
               T tn[6], lp, mp, beta, N[6];
               tn[0] = tang[(int64_t)qp * ne + e];
               if (tn[0] >= 0) {
@@ -470,7 +545,7 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
             }
           }
           if (MS == MS_NH && pc.model == FE_NEOHOOKE) {
-            if (OP == OP_APPLY) {
+            if (APPLY_LIKE) {
               T H0[3][3], FiT[3][3], lnJ;
 #pragma unroll
               for (int c = 0; c < 3; ++c) {
@@ -549,6 +624,20 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
     return;
   }
 
+  // CG: element part of p.Ap = sum_e p_e . K_e p_e (p masked on constrained dofs)
+  double pq = 0;
+  if (OP == OP_CG_APPLY && valid) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            pq += (double)Fo[k][j][i][c] * (double)s_x[3 * ((ex + i) + NX * ((ey + j) + NY * (ez + k))) + c];
+  }
+
   // colour passes: equal index parity => no shared node
   const int color = (ex & 1) | ((ey & 1) << 1) | ((ez & 1) << 2);
   for (int col = 0; col < 8; ++col) {
@@ -583,7 +672,15 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
     const bool priv = (gi == 0 || li >= 1) && (gi == n || li < TX) && (gj == 0 || lj >= 1) && (gj == n || lj < TY) &&
                       (gk == 0 || lk >= 1) && (gk == n || lk < TZ);
     if (a.apply_bc && a.mask && a.mask[dof]) {
-      if (own) Y[dof] = (OP == OP_APPLY) ? X[dof] : T(0);
+      if (own) {
+        if (OP == OP_CG_APPLY) {  // A p = p on constrained dofs; their p.Ap share is p^2
+          const T v = CD[dof] * CR[dof] + cg_beta * CP[dof];
+          Y[dof] = v;
+          pq += (double)v * (double)v;
+        } else {
+          Y[dof] = (OP == OP_APPLY) ? X[dof] : T(0);
+        }
+      }
       continue;
     }
     if (priv)
@@ -591,6 +688,7 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
     else
       atomic_add(Y + dof, s_y[i]);
   }
+  if (OP == OP_CG_APPLY) cg_alpha_arrive(pq, a.ctrl, a.partials, a.counter, &s_red[0][0]);
 }
 
 static int elem_grid(int n) {
@@ -1072,42 +1170,6 @@ hipError_t launch_copy_cvt(const fe_problem* p, const void* src, void* dst, int6
   return hipGetLastError();
 }
 
-// Block sum of a double over VBLOCK lanes; the result is valid in lane 0.
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[w] = v;
-  __syncthreads();
-  double r = 0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < VBLOCK / 64; ++i) r += sh[i];
-  return r;
-}
-
-// Last-block-done: every block publishes partials, the last one to arrive
-// reduces them in block order (deterministic) and resets the counter.
-__device__ __forceinline__ bool arrive_last(unsigned int* counter) {
-  __shared__ bool last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (last) __threadfence();
-  return last;
-}
-
-__device__ __forceinline__ double load_coherent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Sum of partials[0..nb) in fixed order by the whole block; valid in lane 0.
-__device__ __forceinline__ double reduce_partials(const double* partials, int nb, double* sh) {
-  double v = 0;
-  for (int i = threadIdx.x; i < nb; i += VBLOCK) v += load_coherent(partials + i);
-  return block_sum(v, sh);
-}
 
 template <typename T> __global__ __launch_bounds__(VBLOCK) void dot_kernel(const T* a, const T* b, int64_t n,
                                                                             double* partials, unsigned int* counter,
@@ -1141,8 +1203,6 @@ hipError_t launch_dot(const fe_problem* p, const void* a, const void* b, int64_t
 // Jacobi-preconditioned CG with device-resident scalars.  Kernels of an
 // iteration return at once when ctrl->status is set, so the host can enqueue
 // several iterations between convergence checks without changing the result.
-
-__device__ __forceinline__ bool finite(double v) { return v == v && v - v == 0.0; }
 
 // x = 0, r = b, d = 1/d, p = d r, q = 0; rz = r.p, bb = b.b
 template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_init_kernel(
@@ -1280,13 +1340,20 @@ hipError_t cg_init(const fe_problem* p, const void* b, void* x, double rtol, int
                            : cg_init_t(p, (const float*)b, (float*)x, rtol, max_it, s);
 }
 
+int elem_grid_size(int n) { return elem_grid(n); }
+
+// Search-direction buffers of CG iteration k: the fused matrix-free iteration reads
+// p_old and writes p_new, alternating between w_p and w_p2; the CSR iteration keeps p in w_p.
+static void* cg_p_new(const fe_problem* p, int op, long k) {
+  return (op == FE_OP_CSR || (k & 1)) ? p->w_p : p->w_p2;
+}
+
 template <typename T>
 static hipError_t cg_operator_t(const fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const T* vals,
-                                hipStream_t s) {
+                                long k, hipStream_t s) {
   const int* stop = &p->ctrl->status;
-  T* P = (T*)p->w_p;
   T* Q = (T*)p->w_q;
-  if (op == FE_OP_CSR) return launch_spmv_t(p, rp, ci, vals, (const T*)P, Q, stop, s);
+  if (op == FE_OP_CSR) return launch_spmv_t(p, rp, ci, vals, (const T*)p->w_p, Q, stop, s);
   ElemArgs a{};
   a.n = p->n;
   a.h = p->h;
@@ -1294,35 +1361,43 @@ static hipError_t cg_operator_t(const fe_problem* p, int op, const int32_t* rp, 
   a.phase = p->phase;
   a.scale = p->scale;
   a.mask = p->mask;
-  a.x = P;
   a.xlin = p->u_lin;
   a.y = Q;
   a.tangent = p->tangent;
   a.apply_bc = 1;
   a.mat = p->mat;
-  return launch_elem_op<T>(p, OP_APPLY, a, stop, s);
+  a.cg_r = p->w_r;
+  a.cg_dinv = p->w_d;
+  a.cg_pnew = cg_p_new(p, op, k);
+  a.cg_pold = (a.cg_pnew == p->w_p) ? p->w_p2 : p->w_p;
+  a.ctrl = p->ctrl;
+  a.partials = p->partials;
+  a.counter = p->counter;
+  return launch_elem_t<T, OP_CG_APPLY>(p, a, stop, s);
 }
 
-hipError_t cg_operator(const fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals,
+hipError_t cg_operator(const fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, long k,
                        hipStream_t s) {
-  return p->prec == FE_F64 ? cg_operator_t(p, op, rp, ci, (const double*)vals, s)
-                           : cg_operator_t(p, op, rp, ci, (const float*)vals, s);
+  return p->prec == FE_F64 ? cg_operator_t(p, op, rp, ci, (const double*)vals, k, s)
+                           : cg_operator_t(p, op, rp, ci, (const float*)vals, k, s);
 }
 
-template <typename T> static hipError_t cg_vectors_t(const fe_problem* p, T* x, hipStream_t s) {
+template <typename T> static hipError_t cg_vectors_t(const fe_problem* p, int op, T* x, long k, hipStream_t s) {
   const int64_t n = p->n_dof;
-  T* P = (T*)p->w_p;
+  T* P = (T*)cg_p_new(p, op, k);
   T* Q = (T*)p->w_q;
   const dim3 g(vgrid(n)), b(VBLOCK);
-  hipLaunchKernelGGL(cg_alpha_kernel<T>, g, b, 0, s, n, (const T*)P, (const T*)Q, p->ctrl, p->partials, p->counter);
+  if (op == FE_OP_CSR)
+    hipLaunchKernelGGL(cg_alpha_kernel<T>, g, b, 0, s, n, (const T*)P, (const T*)Q, p->ctrl, p->partials, p->counter);
   hipLaunchKernelGGL(cg_update_kernel<T>, g, b, 0, s, n, x, (T*)p->w_r, (const T*)P, Q, (const T*)p->w_d, p->ctrl,
                      p->partials, p->counter);
-  hipLaunchKernelGGL(cg_direction_kernel<T>, g, b, 0, s, n, (const T*)p->w_r, (const T*)p->w_d, P, p->ctrl);
+  if (op == FE_OP_CSR)
+    hipLaunchKernelGGL(cg_direction_kernel<T>, g, b, 0, s, n, (const T*)p->w_r, (const T*)p->w_d, P, p->ctrl);
   return hipGetLastError();
 }
 
-hipError_t cg_vectors(const fe_problem* p, void* x, hipStream_t s) {
-  return p->prec == FE_F64 ? cg_vectors_t(p, (double*)x, s) : cg_vectors_t(p, (float*)x, s);
+hipError_t cg_vectors(const fe_problem* p, int op, void* x, long k, hipStream_t s) {
+  return p->prec == FE_F64 ? cg_vectors_t(p, op, (double*)x, k, s) : cg_vectors_t(p, op, (float*)x, k, s);
 }
 
 // Gauss points of J2 phases and how many of them were plastic at the stored linearisation.

@@ -67,6 +67,9 @@ SIGNATURES = [
     ("fe_profile", _i32, [_vp, _i32]),
     ("fe_profile_read", _i32, [_vp, ctypes.POINTER(_dbl)]),
     ("fe_linearization_stats", _i32, [_vp, ctypes.POINTER(_i64), _vp]),
+    ("fe_mlp_forward", _i32, [_vp, _vp, _vp, _vp, _vp, _i64, _vp]),
+    ("fe_mlp_backward", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp]),
+    ("fe_adam_step", _i32, [_vp, _vp, _vp, _vp, _i64, _dbl, _dbl, _dbl, _dbl, _i32, _vp]),
     ("fe_status_string", ctypes.c_char_p, [_i32]),
     ("fe_last_error", ctypes.c_char_p, []),
 ]
@@ -298,3 +301,45 @@ class Problem:
         out = (_i64 * 2)()
         _check(self.lib.fe_linearization_stats(self.handle, out, _stream()), "fe_linearization_stats")
         return int(out[0]), int(out[1])
+
+
+# ---- surrogate network (float32 device tensors) ---------------------------------------
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 13, 128, 6, 35590
+
+
+def _f32(t, size, name):
+    if t is None:
+        return None
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() != size:
+        raise ValueError(f"{name}: expected a contiguous float32 CUDA tensor of {size} elements")
+    return t
+
+
+def mlp_forward(W, x, jacobian=False, cache=False):
+    """y [n,6] (+ jac [n,6,6] = dy/dx[:, :6], + pre-activation cache [n,3,128])."""
+    lib = load_library()
+    n = x.shape[0]
+    _f32(W, MLP_PARAMS, "W")
+    _f32(x, n * MLP_IN, "x")
+    y = torch.empty(n, MLP_OUT, dtype=torch.float32, device=x.device)
+    jac = torch.empty(n, MLP_OUT, MLP_OUT, dtype=torch.float32, device=x.device) if jacobian else None
+    c = torch.empty(n, 3, MLP_HIDDEN, dtype=torch.float32, device=x.device) if cache else None
+    _check(lib.fe_mlp_forward(_ptr(W), _ptr(x), _ptr(y), _ptr(jac), _ptr(c), n, _stream()), "fe_mlp_forward")
+    return y, jac, c
+
+
+def mlp_backward(W, x, cache, y, target):
+    """(dW [35590], loss (device double scalar)) of the mean squared error of one batch."""
+    lib = load_library()
+    n = x.shape[0]
+    dW = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float64, device=x.device)
+    _check(lib.fe_mlp_backward(_ptr(W), _ptr(x), _ptr(cache), _ptr(y), _ptr(target), _ptr(dW), _ptr(loss), n,
+                               _stream()), "fe_mlp_backward")
+    return dW, loss
+
+
+def adam_step(W, dW, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    lib = load_library()
+    _check(lib.fe_adam_step(_ptr(W), _ptr(dW), _ptr(m), _ptr(v), W.numel(), float(lr), float(beta1), float(beta2),
+                            float(eps), int(t), _stream()), "fe_adam_step")
