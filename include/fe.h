@@ -222,13 +222,42 @@ enum { FE_MLP_IN = 13, FE_MLP_HIDDEN = 128, FE_MLP_OUT = 6, FE_MLP_PARAMS = 3559
 int fe_mlp_forward(const float* W, const float* x, float* y, float* jac, float* cache, int64_t n, void* stream);
 
 /* Gradients of L = mean_s sum_o (y - target)^2 over the n samples of one batch:
- * dW (float [FE_MLP_PARAMS]) is overwritten; loss_dev (double [1]) receives L. */
+ * dW (float [FE_MLP_PARAMS]) is overwritten; loss_dev (double [1]) receives L;
+ * work is scratch of float [n][3*128+6] (per-sample pre-activation gradients). */
 int fe_mlp_backward(const float* W, const float* x, const float* cache, const float* y, const float* target,
-                    float* dW, double* loss_dev, int64_t n, void* stream);
+                    float* dW, double* loss_dev, float* work, int64_t n, void* stream);
 
 /* One Adam step (Kingma & Ba), t >= 1: m, v are the first/second moment buffers. */
 int fe_adam_step(float* W, const float* dW, float* m, float* v, int64_t n_param, double lr, double beta1,
                  double beta2, double eps, int t, void* stream);
+
+/* Use the network as the constitutive law at J2 points whose elastic trial is
+ * plastic (elsewhere, and in other phases, the exact laws apply).  The network
+ * interface is normalised by the first J2 phase: inputs
+ * [eps - eps_p_n, eps_p_n] in Mandel form (shears times sqrt 2 of the tensor
+ * components) and alpha_n, divided by sigma_y / E; output stress in Mandel
+ * form divided by sigma_y.  From the predicted stress the point's plastic
+ * strain is eps - C^-1 sigma and alpha grows by sqrt(2/3) |d eps_p|; where the
+ * prediction's local check max(|q - sigma_y - H alpha| / sigma_y,
+ * |dev s / |dev s| - N_trial|) exceeds fallback_tol the exact radial return is
+ * used instead.  The tangent of accepted points is the symmetric part of the
+ * network Jacobian (the linear solver is CG).  W (float [FE_MLP_PARAMS],
+ * device) is borrowed until the next call; NULL switches the surrogate off.
+ * Every fe_residual then runs three launches (list plastic-trial points,
+ * network, residual) and synchronises once. */
+int fe_set_surrogate(fe_problem* p, const float* W, double fallback_tol);
+
+/* After fe_residual with a surrogate: out_host = {points given to the network,
+ * accepted, fallbacks} (synchronises). */
+int fe_surrogate_stats(fe_problem* p, int64_t* out_host, void* stream);
+
+/* Training-sample capture: while set (x != NULL), every fe_residual appends,
+ * at J2 points whose elastic trial is plastic and whose hashed point index
+ * passes a 1-in-stride thinning, the normalised network input x [13] and the
+ * exact return-map stress y [6] (same normalisation as fe_set_surrogate) to the
+ * caller's buffers (float [capacity][13], [capacity][6]) at slot *count_dev
+ * (device unsigned, incremented; slots beyond capacity are dropped). */
+int fe_set_capture(fe_problem* p, float* x, float* y, int64_t capacity, unsigned int* count_dev, int stride);
 
 const char* fe_status_string(int status);
 const char* fe_last_error(void);

@@ -132,6 +132,12 @@ void fe_problem_destroy(fe_problem* p) {
   free_dev(p->csr_rp);
   free_dev(p->csr_ci);
   free_dev(p->csr_v);
+  free_dev(p->sur_map);
+  free_dev(p->sur_x);
+  free_dev(p->sur_y);
+  free_dev(p->sur_jac);
+  free_dev(p->sur_D);
+  free_dev(p->sur_count);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->host_ctrl) (void)hipHostFree(p->host_ctrl);
   if (p->host_buf) (void)hipHostFree(p->host_buf);
@@ -157,7 +163,8 @@ int fe_problem_create(fe_problem** out, int n, int precision) {
   HIPCHK(hipGetDevice(&p->device));
   const size_t rs = real_size(p), vec = rs * p->n_dof;
   int st = FE_OK;
-  const size_t n_part = std::max<size_t>(2 * 1024, (size_t)elem_grid_size(n));
+  const size_t n_part =
+      std::max<size_t>(2 * 1024, (size_t)std::max<int64_t>(elem_grid_size(n), SPMV_MAXGRID) + 2 * CG_UGRID);
   if ((st = alloc((void**)&p->phase, p->n_el)) || (st = alloc(&p->w_r, vec)) || (st = alloc(&p->w_p, vec)) ||
       (st = alloc(&p->w_p2, vec)) || (st = alloc(&p->w_q, vec)) || (st = alloc(&p->w_d, vec)) ||
       (st = alloc((void**)&p->partials, n_part * sizeof(double))) ||
@@ -224,8 +231,12 @@ int fe_set_materials(fe_problem* p, const uint8_t* phase, int n_phases, const in
     std::vector<uint8_t> h(p->n_el);
     HIPCHK(hipMemcpyAsync(h.data(), phase, p->n_el, hipMemcpyDeviceToHost, S(stream)));
     HIPCHK(hipStreamSynchronize(S(stream)));
-    for (uint8_t v : h)
+    int64_t n_j2 = 0;
+    for (uint8_t v : h) {
       if (v >= n_phases) return arg_error("phase id >= n_phases");
+      n_j2 += models[v] == FE_J2;
+    }
+    p->n_j2_el = n_j2;
   }
   HIPCHK(hipMemcpyAsync(p->phase, phase, p->n_el, hipMemcpyDeviceToDevice, S(stream)));
   if (scale) {
@@ -289,6 +300,8 @@ static ElemArgs base_args(const fe_problem* p) {
   a.tangent = p->tangent;
   a.flags = p->flags;
   a.mat = p->mat;
+  a.sur_map = p->sur_map;
+  a.sur_D = p->sur_D;
   return a;
 }
 
@@ -304,6 +317,53 @@ static int residual_impl(fe_problem* p, const void* u, const void* state_in, voi
   a.store_tangent = (flags & FE_STORE_TANGENT) ? 1 : 0;
   a.apply_bc = (flags & FE_APPLY_BC) ? 1 : 0;
   a.stress_sum = stress_sum;
+  const bool j2 = p->model_set == MS_J2;
+  if (j2 && (p->sur_W || p->cap_x)) {
+    // normalisation of the network interface by the first J2 phase: strains by sigma_y / E, stress by sigma_y
+    for (int i = 0; i < p->mat.n; ++i)
+      if (p->mat.ph[i].model == FE_J2) {
+        const double E = 9.0 * p->mat.ph[i].K * p->mat.ph[i].G / (3.0 * p->mat.ph[i].K + p->mat.ph[i].G);
+        a.sur_sin = (float)(p->mat.ph[i].sy / E);
+        a.sur_sout = (float)p->mat.ph[i].sy;
+        break;
+      }
+  }
+  if (j2 && p->sur_W) {
+    // 1) list the points whose elastic trial is plastic, with their network inputs
+    HIPCHK(hipMemsetAsync(p->sur_count, 0, 3 * sizeof(unsigned int), s));
+    ElemArgs c = a;
+    c.y = nullptr;
+    c.state_out = nullptr;
+    c.store_tangent = 0;
+    c.stress_sum = nullptr;
+    c.sur_mode = SUR_CLASSIFY;
+    c.sur_map = p->sur_map;
+    c.sur_count = p->sur_count;
+    c.sur_cap = p->sur_cap;
+    c.sur_x = p->sur_x;
+    HIPCHK(launch_elem(p, OP_RESID, c, s));
+    HIPCHK(hipMemcpyAsync(p->host_buf, p->sur_count, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int64_t listed = std::min<int64_t>(*reinterpret_cast<unsigned int*>(p->host_buf), p->sur_cap);
+    // 2) network value and Jacobian for the listed points
+    if (int st = fe_mlp_forward(p->sur_W, p->sur_x, p->sur_y, p->sur_jac, nullptr, listed, s)) return st;
+    // 3) residual with the network's stresses where the local check passes
+    a.sur_mode = SUR_CONSUME;
+    a.sur_map = p->sur_map;
+    a.sur_y = p->sur_y;
+    a.sur_jac = p->sur_jac;
+    a.sur_D = p->sur_D;
+    a.sur_stats = p->sur_count + 1;
+    a.sur_tol = p->sur_tol;
+  } else if (j2 && p->cap_x) {
+    a.sur_mode = SUR_CAPTURE;
+    a.sur_count = p->cap_count;
+    a.sur_cap = p->cap_n;
+    a.sur_x = p->cap_x;
+    a.sur_y = p->cap_y;
+    a.sur_stride = p->cap_stride;
+    a.sur_salt = p->cap_salt++ * 0x9E3779B9u;
+  }
   PROF(p, s, 2, launch_elem(p, OP_RESID, a, s));
   if (a.store_tangent) {
     if (p->model_set == MS_NH) HIPCHK(hipMemcpyAsync(p->u_lin, u, rs * p->n_dof, hipMemcpyDeviceToDevice, s));
@@ -430,6 +490,7 @@ static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, 
   long k = 0;
   for (;;) {
     for (int c = 0; c < chunk; ++c, ++k) {
+      HIPCHK(cg_pre(p, op, k, s));
       PROF(p, s, cls, cg_operator(p, op, rp, ci, vals, k, s));
       HIPCHK(cg_vectors(p, op, x, k, s));
     }
@@ -683,5 +744,67 @@ extern "C" int fe_linearization_stats(fe_problem* p, int64_t* out, void* stream)
   const unsigned long long* h = reinterpret_cast<const unsigned long long*>(p->host_buf);
   out[0] = (int64_t)h[0];
   out[1] = (int64_t)h[1];
+  return FE_OK;
+}
+
+extern "C" int fe_set_surrogate(fe_problem* p, const float* W, double tol) {
+  CHKP(p);
+  if (!W) {
+    p->sur_W = nullptr;
+    return FE_OK;
+  }
+  if (p->model_set != MS_J2) return arg_error("the surrogate replaces a J2 phase: set J2 materials first");
+  if (!(tol >= 0)) return arg_error("fallback_tol must be >= 0");
+  const int64_t cap = 8 * p->n_j2_el;
+  if (cap >= (int64_t(1) << 31)) return arg_error("too many J2 points for the surrogate list");
+  if (p->sur_cap < cap) {
+    free_dev(p->sur_x);
+    free_dev(p->sur_y);
+    free_dev(p->sur_jac);
+    free_dev(p->sur_D);
+    p->sur_x = p->sur_y = p->sur_jac = nullptr;
+    p->sur_D = nullptr;
+    p->sur_cap = 0;
+    const int64_t c = std::max<int64_t>(cap, 1);
+    if (alloc((void**)&p->sur_x, sizeof(float) * 13 * c) || alloc((void**)&p->sur_y, sizeof(float) * 6 * c) ||
+        alloc((void**)&p->sur_jac, sizeof(float) * 36 * c) || alloc(&p->sur_D, real_size(p) * 36 * c))
+      return FE_ERR_OOM;
+    p->sur_cap = c;
+  }
+  if (!p->sur_map && alloc((void**)&p->sur_map, sizeof(int) * 8 * p->n_el)) return FE_ERR_OOM;
+  if (!p->sur_count && alloc((void**)&p->sur_count, 4 * sizeof(unsigned int))) return FE_ERR_OOM;
+  p->sur_W = W;
+  p->sur_tol = tol;
+  p->lin_valid = false;  // stored tangents of an earlier law no longer apply
+  return FE_OK;
+}
+
+extern "C" int fe_surrogate_stats(fe_problem* p, int64_t* out, void* stream) {
+  CHKP(p);
+  if (!out) return arg_error("out is null");
+  out[0] = out[1] = out[2] = 0;
+  if (!p->sur_count) return FE_OK;
+  unsigned int* h = reinterpret_cast<unsigned int*>(p->host_buf);
+  HIPCHK(hipMemcpyAsync(h, p->sur_count, 3 * sizeof(unsigned int), hipMemcpyDeviceToHost, S(stream)));
+  HIPCHK(hipStreamSynchronize(S(stream)));
+  out[0] = std::min<int64_t>(h[0], p->sur_cap);
+  out[1] = h[1];
+  out[2] = h[2];
+  return FE_OK;
+}
+
+extern "C" int fe_set_capture(fe_problem* p, float* x, float* y, int64_t capacity, unsigned int* count, int stride) {
+  CHKP(p);
+  if (!x) {
+    p->cap_x = nullptr;
+    return FE_OK;
+  }
+  if (!y || !count || capacity < 1 || stride < 1) return arg_error("capture needs y, count, capacity >= 1, stride >= 1");
+  if (p->model_set != MS_J2) return arg_error("capture records J2 return-map samples: set J2 materials first");
+  p->cap_x = x;
+  p->cap_y = y;
+  p->cap_n = capacity;
+  p->cap_count = count;
+  p->cap_stride = (unsigned)stride;
   return FE_OK;
 }

@@ -30,6 +30,9 @@ struct Phases {
 // Which constitutive models a launch has to handle (selects a kernel instance).
 enum ModelSet { MS_LINEAR = 0, MS_J2 = 1, MS_NH = 2 };
 
+enum SurMode { SUR_OFF = 0, SUR_CAPTURE = 1, SUR_CLASSIFY = 2, SUR_CONSUME = 3 };
+constexpr float SUR_FLAG = -2.0f;  // first stored-tangent word of a point whose tangent comes from the surrogate
+
 // Element-kernel operations.
 enum ElemOp {
   OP_RESID = 0,   // r = sum_e A_e^T r_e(u)        (+ state / linearisation side outputs)
@@ -41,16 +44,19 @@ enum ElemOp {
 // CG status word: kernels stop on any non-zero value, so "converged" must differ from 0.
 constexpr int CG_RUNNING = 0;
 constexpr int CG_CONVERGED = -1;
+constexpr int CG_UGRID = 256;        // workgroups of the CG vector kernels (= update partial slots)
+constexpr int SPMV_MAXGRID = 2048;   // workgroups of the CG mat-vec (grid-stride over rows)
 
 // Device scalar block used by CG (one per problem).
 struct CgCtrl {
-  double rz;        // r.z of the current iterate
-  double pq;        // p.Ap of the current iteration
+  double rz[2];     // r.M^-1 r after update k-1, slot k&1 (written by the direction step of iteration k)
+  double pq;        // p.Ap of the last operator
   double alpha, beta;
-  double rr;        // ||r||^2
+  double rr;        // ||r||^2 at the last direction step
   double bb;        // ||b||^2
   double tol2;      // rtol^2 ||b||^2
-  int iters;
+  double rtol2;     // rtol^2
+  int iters;        // completed updates
   int status;       // CG_RUNNING, CG_CONVERGED or an fe_status error code
   int max_it;
   int pad;
@@ -75,14 +81,28 @@ struct ElemArgs {
   int apply_bc;
   int store_tangent;
   Phases mat;
+  // learned surrogate at J2 points whose elastic trial is plastic
+  int sur_mode;           // SUR_OFF / SUR_CAPTURE / SUR_CLASSIFY / SUR_CONSUME
+  int* sur_map;           // [8][n_el] list slot of each point, -1 if none
+  unsigned int* sur_count;
+  int64_t sur_cap;
+  float* sur_x;           // [cap][13] normalised network inputs
+  float* sur_y;           // [cap][6] capture: normalised stress; consume: network output
+  const float* sur_jac;   // [cap][6][6] network Jacobian (consume)
+  void* sur_D;            // [cap][36] real: symmetrised Voigt tangent of accepted points
+  unsigned int* sur_stats;// [2] accepted, fallback
+  float sur_sin, sur_sout;
+  double sur_tol;
+  unsigned int sur_stride, sur_salt;
   // OP_CG_APPLY only
   const void* cg_r;       // residual r
   const void* cg_dinv;    // inverse Jacobi diagonal
   const void* cg_pold;    // previous search direction
   void* cg_pnew;          // new search direction (written)
   CgCtrl* ctrl;
-  double* partials;
-  unsigned int* counter;
+  double* cg_pa;          // per-workgroup partials of p.Ap (written)
+  const double* cg_pu;    // partials of the previous update (r.r, r.M^-1 r)
+  long cg_k;              // iteration index
 };
 
 template <typename T> struct Buf { T* p = nullptr; };
@@ -123,6 +143,22 @@ struct fe_problem {
   void* csr_v = nullptr;
   fe::CgCtrl* host_ctrl = nullptr;  // pinned
   double* host_buf = nullptr;       // pinned scratch
+  // learned surrogate (fe_set_surrogate) and sample capture (fe_set_capture)
+  int64_t n_j2_el = 0;              // elements of J2 phases
+  const float* sur_W = nullptr;     // network parameters (caller-owned)
+  double sur_tol = 0;
+  int64_t sur_cap = 0;
+  int* sur_map = nullptr;
+  float* sur_x = nullptr;
+  float* sur_y = nullptr;
+  float* sur_jac = nullptr;
+  void* sur_D = nullptr;
+  unsigned int* sur_count = nullptr;   // [0] list length, [1] accepted, [2] fallback
+  float* cap_x = nullptr;              // capture: caller buffers
+  float* cap_y = nullptr;
+  int64_t cap_n = 0;
+  unsigned int* cap_count = nullptr;
+  unsigned int cap_stride = 1, cap_salt = 0;
   // kernel timing (fe_profile): event pairs around selected launches
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -156,6 +192,9 @@ hipError_t launch_csr_diag(const fe_problem* p, const int32_t* rp, const int32_t
 hipError_t launch_copy_cvt(const fe_problem* p, const void* src, void* dst, int64_t n, hipStream_t s);
 
 hipError_t launch_lin_stats(const fe_problem* p, unsigned long long* out, hipStream_t s);
+// network forward + Jacobian over a device-counted list (blocks beyond *count return)
+hipError_t launch_mlp_forward_counted(const float* W, const float* x, float* y, float* jac, int64_t cap,
+                                      const unsigned int* count, hipStream_t s);
 
 // CG pieces: one iteration = cg_operator (q = A p) then cg_vectors (scalars and updates)
 hipError_t cg_init(const fe_problem* p, const void* b, void* x, double rtol, int max_it, hipStream_t s);
@@ -163,6 +202,9 @@ hipError_t cg_init(const fe_problem* p, const void* b, void* x, double rtol, int
 hipError_t cg_operator(const fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, long k,
                        hipStream_t s);
 hipError_t cg_vectors(const fe_problem* p, int op, void* x, long k, hipStream_t s);
+hipError_t cg_pre(const fe_problem* p, int op, long k, hipStream_t s);  // CSR: direction kernel before the mat-vec
 int elem_grid_size(int n);  // workgroups of an element-kernel launch (also the partial-sum slots it needs)
+// partial-sum slots of a CG operator launch; the update partials (2 * CG_UGRID) follow them
+inline int64_t cg_pa_size(const fe_problem* p) { return std::max<int64_t>(elem_grid_size(p->n), SPMV_MAXGRID); }
 
 }  // namespace fe

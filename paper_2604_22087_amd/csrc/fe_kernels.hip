@@ -77,24 +77,61 @@ __device__ __forceinline__ double reduce_partials(const double* partials, int nb
 
 __device__ __forceinline__ bool finite(double v) { return v == v && v - v == 0.0; }
 
-// CG step length from the block partials of p.Ap (last block): alpha = rz / pAp.
-__device__ __forceinline__ void cg_alpha_arrive(double v, CgCtrl* ctrl, double* partials, unsigned int* counter,
-                                                double* sh) {
+// Wavefront-aggregated append: lanes with pred set get consecutive slots of *counter
+// (one atomic per wave).  Valid for any set of active lanes.
+__device__ __forceinline__ unsigned wave_append(unsigned int* counter, bool pred) {
+  const unsigned long long m = __ballot(pred);
+  if (m == 0) return 0;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)m) - 1;
+  unsigned base = 0;
+  if (lane == leader) base = atomicAdd(counter, (unsigned)__popcll(m));
+  base = __shfl(base, leader, 64);
+  return base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+}
+
+__device__ __forceinline__ void wave_count(unsigned int* counter, bool pred) {
+  const unsigned long long m = __ballot(pred);
+  if (m != 0 && __lane_id() == __ffsll((long long)m) - 1) atomicAdd(counter, (unsigned)__popcll(m));
+}
+
+// Block-wide sum of partials[0..nb), returned to every thread.
+__device__ __forceinline__ double sum_partials_all(const double* partials, int nb, double* sh, double* bc) {
+  double v = 0;
+  for (int i = threadIdx.x; i < nb; i += 256) v += partials[i];
   v = block_sum(v, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = v;
-  if (arrive_last(counter)) {
-    const double pq = reduce_partials(partials, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-      ctrl->pq = pq;
-      if (!finite(pq))
-        ctrl->status = FE_ERR_NONFINITE;
-      else if (pq <= 0.0)
-        ctrl->status = FE_ERR_BREAKDOWN;
-      else
-        ctrl->alpha = ctrl->rz / pq;
-      *counter = 0;
+  if (threadIdx.x == 0) *bc = v;
+  __syncthreads();
+  return *bc;
+}
+
+// CG direction step of iteration k (see the CG section below); false when the
+// iteration stops (block 0 records the status).
+__device__ __forceinline__ bool cg_direction_step(CgCtrl* ctrl, const double* pu, long k, double* sh, double* bc,
+                                                  double& beta) {
+  const double rr = sum_partials_all(pu, CG_UGRID, sh, bc);
+  const double rz = sum_partials_all(pu + CG_UGRID, CG_UGRID, sh, bc + 1);
+  const double tol2 = k == 0 ? ctrl->rtol2 * rr : ctrl->tol2;
+  int st = CG_RUNNING;
+  if (!finite(rr) || !finite(rz))
+    st = FE_ERR_NONFINITE;
+  else if (k == 0 ? rr == 0.0 : rr <= tol2)
+    st = CG_CONVERGED;
+  else if (k >= ctrl->max_it)
+    st = FE_ERR_NOT_CONVERGED;
+  beta = k == 0 ? 0.0 : rz / ctrl->rz[(k - 1) & 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (k == 0) {
+      ctrl->bb = rr;
+      ctrl->tol2 = tol2;
     }
+    ctrl->rr = rr;
+    ctrl->iters = (int)k;
+    ctrl->beta = beta;
+    ctrl->rz[k & 1] = rz;
+    if (st != CG_RUNNING) ctrl->status = st;
   }
+  return st == CG_RUNNING;
 }
 
 // G[r][q] = sum_{k,j} M[r][k] M[q][j] D[k][j] with M = [[GA,GB],[GB,GA]] (M symmetric,
@@ -303,6 +340,92 @@ __device__ __forceinline__ void j2_apply(const T H[3][3], T lp, T mp, T beta, co
   S[0][1] = S[1][0] = 2 * mp * e01 - bn * N[5];
 }
 
+// ---- learned surrogate at a plastic-trial J2 point ----------------------------------
+constexpr double RSQ2 = 0.70710678118654752440;  // 1/sqrt(2)
+
+// Normalised network inputs [eps - eps_p_n, eps_p_n] (Mandel: shear = gamma / sqrt 2), alpha_n; / s_in.
+template <typename T>
+__device__ __forceinline__ void sur_inputs(const T H[3][3], const T epn[6], T an, float s_in, float* x) {
+  const T e[6] = {H[0][0], H[1][1], H[2][2], H[1][2] + H[2][1], H[0][2] + H[2][0], H[0][1] + H[1][0]};
+  const T inv = T(1) / T(s_in);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const T c = k < 3 ? T(1) : T(RSQ2);
+    x[k] = float((e[k] - epn[k]) * c * inv);
+    x[6 + k] = float(epn[k] * c * inv);
+  }
+  x[12] = float(an * inv);
+}
+
+// Stress, history and symmetrised Voigt tangent from the network output y (normalised
+// Mandel stress) and Jacobian J = dy/dx[:, :6]; false when the local check exceeds tol.
+template <typename T>
+__device__ __forceinline__ bool sur_consume(const T H[3][3], const T epn[6], T an, T K, T G, T sy, T Hh,
+                                            const float* y, const float* J, float s_in, float s_out, double tol,
+                                            const T tn[6], T S[3][3], T ep[6], T& al, T* Dsym) {
+  const T c[6] = {T(1), T(1), T(1), T(RSQ2), T(RSQ2), T(RSQ2)};
+  T sig[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) sig[i] = T(s_out) * T(y[i]) * c[i];
+  // elastic strain C^-1 sigma (engineering shear) -> plastic strain and hardening variable
+  const T lam = K - T(2.0 / 3.0) * G;
+  const T trs = sig[0] + sig[1] + sig[2];
+  const T a = lam / (2 * G + 3 * lam);
+  const T e[6] = {H[0][0], H[1][1], H[2][2], H[1][2] + H[2][1], H[0][2] + H[2][0], H[0][1] + H[1][0]};
+  T dsq = 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const T ee = k < 3 ? (sig[k] - a * trs) / (2 * G) : sig[k] / G;
+    ep[k] = e[k] - ee;
+    const T d = ep[k] - epn[k];
+    dsq += k < 3 ? d * d : T(0.5) * d * d;
+  }
+  al = an + sqrt(T(2.0 / 3.0) * dsq);
+  // local check: yield condition and flow direction of the prediction
+  const T m = trs / T(3);
+  const T d0 = sig[0] - m, d1 = sig[1] - m, d2 = sig[2] - m;
+  const T dn = sqrt(d0 * d0 + d1 * d1 + d2 * d2 + 2 * (sig[3] * sig[3] + sig[4] * sig[4] + sig[5] * sig[5]));
+  const T q = T(SQRT1_5) * dn;
+  const T r1 = fabs(q - sy - Hh * al) / sy;
+  const T idn = dn > 0 ? T(1) / dn : T(1);
+  const T nzz = -(tn[1] + tn[2]);
+  const T f0 = d0 * idn - tn[1], f1 = d1 * idn - tn[2], f2 = d2 * idn - nzz;
+  const T f3 = sig[3] * idn - tn[3], f4 = sig[4] * idn - tn[4], f5 = sig[5] * idn - tn[5];
+  const T r2 = sqrt(f0 * f0 + f1 * f1 + f2 * f2 + 2 * (f3 * f3 + f4 * f4 + f5 * f5));
+  if (!(fmax(r1, r2) <= T(tol))) return false;
+  S[0][0] = sig[0];
+  S[1][1] = sig[1];
+  S[2][2] = sig[2];
+  S[1][2] = S[2][1] = sig[3];
+  S[0][2] = S[2][0] = sig[4];
+  S[0][1] = S[1][0] = sig[5];
+  const T f = T(s_out) / T(s_in);
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) Dsym[i * 6 + j] = T(0.5) * f * c[i] * c[j] * (T(J[i * 6 + j]) + T(J[j * 6 + i]));
+  return true;
+}
+
+// Stress from a general Voigt tangent D (tensor stress, engineering shear strain) and sym(H).
+template <typename T> __device__ __forceinline__ void general_apply(const T H[3][3], const T* D, T S[3][3]) {
+  const T e[6] = {H[0][0], H[1][1], H[2][2], H[1][2] + H[2][1], H[0][2] + H[2][0], H[0][1] + H[1][0]};
+  T s[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    T acc = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) acc += D[i * 6 + j] * e[j];
+    s[i] = acc;
+  }
+  S[0][0] = s[0];
+  S[1][1] = s[1];
+  S[2][2] = s[2];
+  S[1][2] = S[2][1] = s[3];
+  S[0][2] = S[2][0] = s[4];
+  S[0][1] = S[1][0] = s[5];
+}
+
 // Neo-Hookean kinematics: F = I + H, J - 1 without cancellation, ln J, F^-T.
 // Returns false when J <= 0.
 template <typename T>
@@ -387,6 +510,7 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
   __shared__ T s_y[OP == OP_VJP ? 1 : NN * 3];
   __shared__ T s_l[NEED_L ? NN * 3 : 1];
   __shared__ double s_red[6][EBLOCK / 64];
+  __shared__ double s_bc[2];
 
   if (stop && *stop) return;
   const int n = a.n;
@@ -396,7 +520,7 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
   const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
   if (tile >= nb) {
     // padding block of the XCD-aware numbering: still takes part in the p.Ap reduction
-    if (OP == OP_CG_APPLY) cg_alpha_arrive(0.0, a.ctrl, a.partials, a.counter, &s_red[0][0]);
+    if (OP == OP_CG_APPLY && threadIdx.x == 0) a.cg_pa[blockIdx.x] = 0.0;
     return;
   }
   const int a0 = (tile % ntx) * TX, b0 = ((tile / ntx) % nty) * TY, c0 = (tile / (ntx * nty)) * TZ;
@@ -407,7 +531,12 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
   const T* CD = static_cast<const T*>(a.cg_dinv);
   const T* CP = static_cast<const T*>(a.cg_pold);
   T* CPN = static_cast<T*>(a.cg_pnew);
-  const T cg_beta = (OP == OP_CG_APPLY) ? T(a.ctrl->beta) : T(0);
+  T cg_beta = T(0);
+  if (OP == OP_CG_APPLY) {  // direction step of this CG iteration (same decision in every workgroup)
+    double beta;
+    if (!cg_direction_step(a.ctrl, a.cg_pu, a.cg_k, &s_red[0][0], s_bc, beta)) return;
+    cg_beta = T(beta);
+  }
   const int64_t np1 = n + 1;
 
   for (int i = tid; i < NN * 3; i += EBLOCK) {
@@ -519,6 +648,53 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
               for (int k = 0; k < 6; ++k) epn[k] = st_in ? st_in[(int64_t)(k * 8 + qp) * ne + e] : T(0);
               if (st_in) an = st_in[(int64_t)(6 * 8 + qp) * ne + e];
               j2_update(H, epn, an, Kb, Gs, sy, Hh, S, ep, al, tn);
+              if (a.sur_mode != SUR_OFF) {
+                const int64_t pidx = (int64_t)qp * ne + e;
+                const bool ptrial = tn[0] >= 0;  // elastic trial is plastic: the surrogate's domain
+                if (a.sur_mode == SUR_CAPTURE) {
+                  const bool keep = ptrial && (((unsigned)pidx * 2654435761u + a.sur_salt) % a.sur_stride == 0);
+                  const unsigned slot = wave_append(a.sur_count, keep);
+                  if (keep && slot < a.sur_cap) {
+                    sur_inputs(H, epn, an, a.sur_sin, a.sur_x + (int64_t)slot * 13);
+                    const T rt2 = T(1.41421356237309504880), is = T(1) / T(a.sur_sout);
+                    float* yo = a.sur_y + (int64_t)slot * 6;
+                    yo[0] = float(S[0][0] * is);
+                    yo[1] = float(S[1][1] * is);
+                    yo[2] = float(S[2][2] * is);
+                    yo[3] = float(S[1][2] * rt2 * is);
+                    yo[4] = float(S[0][2] * rt2 * is);
+                    yo[5] = float(S[0][1] * rt2 * is);
+                  }
+                } else if (a.sur_mode == SUR_CLASSIFY) {
+                  const unsigned slot = wave_append(a.sur_count, ptrial);
+                  const bool listed = ptrial && slot < a.sur_cap;
+                  a.sur_map[pidx] = listed ? (int)slot : -1;
+                  if (listed) sur_inputs(H, epn, an, a.sur_sin, a.sur_x + (int64_t)slot * 13);
+                } else {  // SUR_CONSUME
+                  const int slot = a.sur_map[pidx];
+                  bool accepted = false, fallback = false;
+                  if (ptrial && slot >= 0) {
+                    T Ss[3][3], eps2[6], al2;
+                    T* Dsym = static_cast<T*>(a.sur_D) + (int64_t)slot * 36;
+                    accepted = sur_consume(H, epn, an, Kb, Gs, sy, Hh, a.sur_y + (int64_t)slot * 6,
+                                           a.sur_jac + (int64_t)slot * 36, a.sur_sin, a.sur_sout, a.sur_tol, tn,
+                                           Ss, eps2, al2, Dsym);
+                    fallback = !accepted;
+                    if (accepted) {
+#pragma unroll
+                      for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) S[i][j] = Ss[i][j];
+#pragma unroll
+                      for (int k = 0; k < 6; ++k) ep[k] = eps2[k];
+                      al = al2;
+                      tn[0] = T(SUR_FLAG);
+                    }
+                  }
+                  wave_count(a.sur_stats, accepted);
+                  wave_count(a.sur_stats + 1, fallback);
+                }
+              }
               if (st_out) {
 #pragma unroll
                 for (int k = 0; k < 6; ++k) st_out[(int64_t)(k * 8 + qp) * ne + e] = ep[k];
@@ -532,15 +708,20 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
             } else if (APPLY_LIKE) {
               T tn[6], lp, mp, beta, N[6];
               tn[0] = tang[(int64_t)qp * ne + e];
-              if (tn[0] >= 0) {
-#pragma unroll
-                for (int k = 1; k < 6; ++k) tn[k] = tang[(int64_t)(k * 8 + qp) * ne + e];
+              if (tn[0] < T(-1.5)) {  // surrogate tangent of this point
+                const int slot = a.sur_map[(int64_t)qp * ne + e];
+                general_apply(H, static_cast<const T*>(a.sur_D) + (int64_t)slot * 36, S);
               } else {
+                if (tn[0] >= 0) {
 #pragma unroll
-                for (int k = 1; k < 6; ++k) tn[k] = 0;
+                  for (int k = 1; k < 6; ++k) tn[k] = tang[(int64_t)(k * 8 + qp) * ne + e];
+                } else {
+#pragma unroll
+                  for (int k = 1; k < 6; ++k) tn[k] = 0;
+                }
+                j2_tangent_coeffs(tn, Kb, Gs, Hh, lp, mp, beta, N);
+                j2_apply(H, lp, mp, beta, N, S);
               }
-              j2_tangent_coeffs(tn, Kb, Gs, Hh, lp, mp, beta, N);
-              j2_apply(H, lp, mp, beta, N, S);
               done = true;
             }
           }
@@ -609,6 +790,17 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
 
   if (OP == OP_VJP) {
     if (valid) {
+      // the element's nodal forces sum to zero, so lambda may be taken relative to its
+      // element mean: exact, and it removes the cancellation of a large rigid part
+      double lm[3] = {0, 0, 0};
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) lm[c] += (double)s_l[3 * ((ex + i) + NX * ((ey + j) + NY * (ez + k))) + c];
       double d = 0;
 #pragma unroll
       for (int k = 0; k < 2; ++k)
@@ -618,7 +810,8 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
           for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-              d += (double)Fo[k][j][i][c] * (double)s_l[3 * ((ex + i) + NX * ((ey + j) + NY * (ez + k))) + c];
+              d += (double)Fo[k][j][i][c] *
+                   ((double)s_l[3 * ((ex + i) + NX * ((ey + j) + NY * (ez + k))) + c] - 0.125 * lm[c]);
       static_cast<T*>(a.out_el)[e] = T(d);
     }
     return;
@@ -688,7 +881,10 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
     else
       atomic_add(Y + dof, s_y[i]);
   }
-  if (OP == OP_CG_APPLY) cg_alpha_arrive(pq, a.ctrl, a.partials, a.counter, &s_red[0][0]);
+  if (OP == OP_CG_APPLY) {
+    const double t = block_sum(pq, &s_red[0][0]);
+    if (threadIdx.x == 0) a.cg_pa[blockIdx.x] = t;
+  }
 }
 
 static int elem_grid(int n) {
@@ -745,12 +941,15 @@ struct TanArgs {
   const void* tangent;
   const uint8_t* mask;
   Phases mat;
+  const int* sur_map;   // surrogate points: slot of their general Voigt tangent in sur_D
+  const void* sur_D;
 };
 
 template <typename T> struct QpTangent {
-  int kind;  // 0: small strain D = lp 1x1 + 2 mp I_sym - beta N x N; 1: Neo-Hookean at F
+  int kind;  // 0: small strain D = lp 1x1 + 2 mp I_sym - beta N x N; 1: Neo-Hookean at F; 2: general Voigt D
   T lp, mp, beta, N[6];
   T mu, lam, lnJ, FiT[3][3];
+  const T* D;
 };
 
 template <typename T, int MS>
@@ -769,7 +968,12 @@ __device__ __forceinline__ void load_qp_tangent(const TanArgs& a, int64_t e, int
     T tn[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) tn[k] = tg[(int64_t)(k * 8 + qp) * ne + e];
-    j2_tangent_coeffs(tn, T(pc.K) * sc, T(pc.G) * sc, T(pc.H), t.lp, t.mp, t.beta, t.N);
+    if (tn[0] < T(-1.5)) {
+      t.kind = 2;
+      t.D = static_cast<const T*>(a.sur_D) + (int64_t)a.sur_map[(int64_t)qp * ne + e] * 36;
+    } else {
+      j2_tangent_coeffs(tn, T(pc.K) * sc, T(pc.G) * sc, T(pc.H), t.lp, t.mp, t.beta, t.N);
+    }
   }
   if (MS == MS_NH && pc.model == FE_NEOHOOKE) {
     t.kind = 1;
@@ -787,7 +991,32 @@ __device__ __forceinline__ void load_qp_tangent(const TanArgs& a, int64_t e, int
 template <typename T>
 __device__ __forceinline__ void block_add(const QpTangent<T>& t, const T ga[3], const T gb[3], T w, T B[3][3]) {
   const T dot = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
-  if (t.kind == 0) {
+  if (t.kind == 2) {
+    // B_a^T D B_b with the 6x3 strain-displacement blocks of the two nodes
+    const T Ba[6][3] = {{ga[0], 0, 0}, {0, ga[1], 0}, {0, 0, ga[2]},
+                        {0, ga[2], ga[1]}, {ga[2], 0, ga[0]}, {ga[1], ga[0], 0}};
+    const T Bb[6][3] = {{gb[0], 0, 0}, {0, gb[1], 0}, {0, 0, gb[2]},
+                        {0, gb[2], gb[1]}, {gb[2], 0, gb[0]}, {gb[1], gb[0], 0}};
+    T DB[6][3];
+#pragma unroll
+    for (int p = 0; p < 6; ++p)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        T s = 0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) s += t.D[p * 6 + q] * Bb[q][k];
+        DB[p][k] = s;
+      }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        T s = 0;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) s += Ba[p][i] * DB[p][k];
+        B[i][k] += w * s;
+      }
+  } else if (t.kind == 0) {
     const T* N = t.N;  // xx yy zz yz xz xy
     const T na[3] = {N[0] * ga[0] + N[5] * ga[1] + N[4] * ga[2], N[5] * ga[0] + N[1] * ga[1] + N[3] * ga[2],
                      N[4] * ga[0] + N[3] * ga[1] + N[2] * ga[2]};
@@ -824,6 +1053,8 @@ static TanArgs tan_args(const fe_problem* p) {
   a.tangent = p->tangent;
   a.mask = p->mask;
   a.mat = p->mat;
+  a.sur_map = p->sur_map;
+  a.sur_D = p->sur_D;
   return a;
 }
 
@@ -1191,23 +1422,29 @@ template <typename T> __global__ __launch_bounds__(VBLOCK) void dot_kernel(const
 
 hipError_t launch_dot(const fe_problem* p, const void* a, const void* b, int64_t n, double* out, hipStream_t s) {
   if (p->prec == FE_F64)
-    hipLaunchKernelGGL(dot_kernel<double>, dim3(vgrid(n)), dim3(VBLOCK), 0, s, (const double*)a, (const double*)b, n,
+    hipLaunchKernelGGL(dot_kernel<double>, dim3(std::min(vgrid(n), 64)), dim3(VBLOCK), 0, s, (const double*)a, (const double*)b, n,
                        p->partials, p->counter, out);
   else
-    hipLaunchKernelGGL(dot_kernel<float>, dim3(vgrid(n)), dim3(VBLOCK), 0, s, (const float*)a, (const float*)b, n,
+    hipLaunchKernelGGL(dot_kernel<float>, dim3(std::min(vgrid(n), 64)), dim3(VBLOCK), 0, s, (const float*)a, (const float*)b, n,
                        p->partials, p->counter, out);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Jacobi-preconditioned CG with device-resident scalars.  Kernels of an
-// iteration return at once when ctrl->status is set, so the host can enqueue
-// several iterations between convergence checks without changing the result.
+// Jacobi-preconditioned CG with device-resident scalars and no grid-wide fences.
+// Every kernel of an iteration writes per-block partial sums; the next kernel
+// re-reduces them in every block in the same order (identical results in all
+// blocks; the kernel boundary makes the partials visible), and block 0 records
+// the scalars for the host.  Kernels return at once when ctrl->status is set, so
+// the host can enqueue several iterations between convergence checks.
+//   direction step k: rr, rz from the update partials -> stop tests, beta = rz / rz_old,
+//                     p = M^-1 r + beta p          (fused into the matrix-free operator)
+//   operator k:       q = A p, partials of p.q
+//   update k:         alpha = rz / p.q, x += alpha p, r -= alpha q, q = 0, partials of r.r, r.M^-1 r
 
-// x = 0, r = b, d = 1/d, p = d r, q = 0; rz = r.p, bb = b.b
+// x = 0, r = b, q = 0, p = 0, d <- 1/d; partials of b.b and b.M^-1 b (CG_UGRID blocks)
 template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_init_kernel(
-    int64_t n, const T* b, T* x, T* r, T* p, T* q, T* dinv, CgCtrl* ctrl, double rtol, int max_it, double* partials,
-    unsigned int* counter) {
+    int64_t n, const T* b, T* x, T* r, T* p, T* q, T* dinv, CgCtrl* ctrl, double rtol, int max_it, double* pu) {
   __shared__ double sh[VBLOCK / 64];
   double rz = 0, bb = 0;
   for (int64_t i = (int64_t)blockIdx.x * VBLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * VBLOCK) {
@@ -1217,121 +1454,80 @@ template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_init_kernel(
     x[i] = 0;
     r[i] = bi;
     q[i] = 0;
-    const T zi = di * bi;
-    p[i] = zi;
-    rz += (double)bi * (double)zi;
+    p[i] = 0;
+    rz += (double)bi * (double)(di * bi);
     bb += (double)bi * (double)bi;
   }
   rz = block_sum(rz, sh);
   bb = block_sum(bb, sh);
   if (threadIdx.x == 0) {
-    partials[blockIdx.x] = rz;
-    partials[VGRID_MAX + blockIdx.x] = bb;
+    pu[blockIdx.x] = bb;
+    pu[CG_UGRID + blockIdx.x] = rz;
   }
-  if (arrive_last(counter)) {
-    const double trz = reduce_partials(partials, gridDim.x, sh);
-    const double tbb = reduce_partials(partials + VGRID_MAX, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-      ctrl->rz = trz;
-      ctrl->bb = tbb;
-      ctrl->rr = tbb;
-      ctrl->tol2 = rtol * rtol * tbb;
-      ctrl->iters = 0;
-      ctrl->max_it = max_it;
-      ctrl->alpha = ctrl->beta = ctrl->pq = 0;
-      ctrl->status = !finite(trz) || !finite(tbb)
-                         ? FE_ERR_NONFINITE
-                         : (tbb == 0.0 ? CG_CONVERGED : (max_it <= 0 ? FE_ERR_NOT_CONVERGED : CG_RUNNING));
-      *counter = 0;
-    }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl->rz[0] = ctrl->rz[1] = 0;
+    ctrl->rtol2 = rtol * rtol;
+    ctrl->iters = 0;
+    ctrl->max_it = max_it;
+    ctrl->alpha = ctrl->beta = ctrl->pq = 0;
+    ctrl->status = CG_RUNNING;
   }
 }
 
-// pq = p.q  -> alpha = rz / pq (breakdown / non-finite checks)
-template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_alpha_kernel(int64_t n, const T* p, const T* q,
-                                                                                 CgCtrl* ctrl, double* partials,
-                                                                                 unsigned int* counter) {
-  __shared__ double sh[VBLOCK / 64];
+// CSR path: direction step as a kernel of its own (the mat-vec needs the whole p first)
+template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_direction_kernel(int64_t n, const T* r,
+                                                                                     const T* dinv, T* p,
+                                                                                     CgCtrl* ctrl, const double* pu,
+                                                                                     long k) {
+  __shared__ double sh[VBLOCK / 64], bc[2];
   if (ctrl->status) return;
-  double v = 0;
+  double beta;
+  if (!cg_direction_step(ctrl, pu, k, sh, bc, beta)) return;
+  const T tb = T(beta);
   for (int64_t i = (int64_t)blockIdx.x * VBLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * VBLOCK)
-    v += (double)p[i] * (double)q[i];
-  v = block_sum(v, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = v;
-  if (arrive_last(counter)) {
-    const double pq = reduce_partials(partials, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-      ctrl->pq = pq;
-      if (!finite(pq))
-        ctrl->status = FE_ERR_NONFINITE;
-      else if (pq <= 0.0)
-        ctrl->status = FE_ERR_BREAKDOWN;
-      else
-        ctrl->alpha = ctrl->rz / pq;
-      *counter = 0;
-    }
-  }
+    p[i] = dinv[i] * r[i] + tb * p[i];
 }
 
-// x += alpha p; r -= alpha q; q = 0; rr = r.r; rz' = r.(dinv r) -> convergence test, beta
+// alpha = rz / p.q (from the operator's partials); x += alpha p; r -= alpha q; q = 0
 template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_update_kernel(int64_t n, T* x, T* r, const T* p,
                                                                                   T* q, const T* dinv, CgCtrl* ctrl,
-                                                                                  double* partials,
-                                                                                  unsigned int* counter) {
-  __shared__ double sh[VBLOCK / 64];
+                                                                                  const double* pa, int nba,
+                                                                                  double* pu, long k) {
+  __shared__ double sh[VBLOCK / 64], bc[1];
   if (ctrl->status) return;
-  const T alpha = T(ctrl->alpha);
-  double rr = 0, rz = 0;
+  const double pq = sum_partials_all(pa, nba, sh, bc);
+  const double rz = ctrl->rz[k & 1];
+  const int st = !finite(pq) ? FE_ERR_NONFINITE : (pq <= 0.0 ? FE_ERR_BREAKDOWN : CG_RUNNING);
+  const double alpha = rz / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl->pq = pq;
+    ctrl->alpha = alpha;
+    if (st != CG_RUNNING) ctrl->status = st;
+  }
+  if (st != CG_RUNNING) return;
+  const T ta = T(alpha);
+  double rr = 0, rzn = 0;
   for (int64_t i = (int64_t)blockIdx.x * VBLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * VBLOCK) {
-    x[i] += alpha * p[i];
-    const T ri = r[i] - alpha * q[i];
+    x[i] += ta * p[i];
+    const T ri = r[i] - ta * q[i];
     r[i] = ri;
     q[i] = 0;
     rr += (double)ri * (double)ri;
-    rz += (double)ri * (double)(dinv[i] * ri);
+    rzn += (double)ri * (double)(dinv[i] * ri);
   }
   rr = block_sum(rr, sh);
-  rz = block_sum(rz, sh);
+  rzn = block_sum(rzn, sh);
   if (threadIdx.x == 0) {
-    partials[blockIdx.x] = rr;
-    partials[VGRID_MAX + blockIdx.x] = rz;
+    pu[blockIdx.x] = rr;
+    pu[CG_UGRID + blockIdx.x] = rzn;
   }
-  if (arrive_last(counter)) {
-    const double trr = reduce_partials(partials, gridDim.x, sh);
-    const double trz = reduce_partials(partials + VGRID_MAX, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-      ctrl->iters += 1;
-      ctrl->rr = trr;
-      if (!finite(trr) || !finite(trz))
-        ctrl->status = FE_ERR_NONFINITE;
-      else if (trr <= ctrl->tol2)
-        ctrl->status = CG_CONVERGED;
-      else if (ctrl->iters >= ctrl->max_it)
-        ctrl->status = FE_ERR_NOT_CONVERGED;
-      else {
-        ctrl->beta = trz / ctrl->rz;
-        ctrl->rz = trz;
-      }
-      *counter = 0;
-    }
-  }
-}
-
-// p = dinv r + beta p
-template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_direction_kernel(int64_t n, const T* r,
-                                                                                     const T* dinv, T* p,
-                                                                                     const CgCtrl* ctrl) {
-  if (ctrl->status) return;
-  const T beta = T(ctrl->beta);
-  for (int64_t i = (int64_t)blockIdx.x * VBLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * VBLOCK)
-    p[i] = dinv[i] * r[i] + beta * p[i];
 }
 
 template <typename T>
 static hipError_t cg_init_t(const fe_problem* p, const T* b, T* x, double rtol, int max_it, hipStream_t s) {
   const int64_t n = p->n_dof;
-  hipLaunchKernelGGL(cg_init_kernel<T>, dim3(vgrid(n)), dim3(VBLOCK), 0, s, n, b, x, (T*)p->w_r, (T*)p->w_p,
-                     (T*)p->w_q, (T*)p->w_d, p->ctrl, rtol, max_it, p->partials, p->counter);
+  hipLaunchKernelGGL(cg_init_kernel<T>, dim3(CG_UGRID), dim3(VBLOCK), 0, s, n, b, x, (T*)p->w_r, (T*)p->w_p,
+                     (T*)p->w_q, (T*)p->w_d, p->ctrl, rtol, max_it, p->partials + cg_pa_size(p));
   return hipGetLastError();
 }
 
@@ -1348,12 +1544,55 @@ static void* cg_p_new(const fe_problem* p, int op, long k) {
   return (op == FE_OP_CSR || (k & 1)) ? p->w_p : p->w_p2;
 }
 
+// CG mat-vec: q = A p with LPR lanes per row (grid-stride over rows) and per-workgroup partials of p.q.
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void cg_spmv_kernel(int64_t n_rows, const int32_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ ci, const T* __restrict__ v,
+                                                      const T* __restrict__ p, T* __restrict__ q, const int* stop,
+                                                      double* pa) {
+  __shared__ double sh[VBLOCK / 64];
+  if (*stop) return;
+  constexpr int RPB = 256 / LPR;
+  const int lane = threadIdx.x % LPR;
+  double pq = 0;
+  for (int64_t row0 = (int64_t)blockIdx.x * RPB; row0 < n_rows; row0 += (int64_t)gridDim.x * RPB) {
+    const int64_t row = row0 + threadIdx.x / LPR;
+    T acc = 0;
+    if (row < n_rows) {
+      const int b = rp[row], e = rp[row + 1];
+      for (int k = b + lane; k < e; k += LPR) acc += v[k] * p[ci[k]];
+    }
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
+    if (row < n_rows && lane == 0) {
+      q[row] = acc;
+      pq += (double)p[row] * (double)acc;
+    }
+  }
+  pq = block_sum(pq, sh);
+  if (threadIdx.x == 0) pa[blockIdx.x] = pq;
+}
+
+static int cg_spmv_grid(const fe_problem* p) {
+  const int64_t blocks = (p->n_dof + (256 / SPMV_LPR) - 1) / (256 / SPMV_LPR);
+  return (int)std::min<int64_t>(blocks, SPMV_MAXGRID);
+}
+
+static int cg_operator_grid(const fe_problem* p, int op) {
+  return op == FE_OP_CSR ? cg_spmv_grid(p) : elem_grid(p->n);
+}
+
 template <typename T>
 static hipError_t cg_operator_t(const fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const T* vals,
                                 long k, hipStream_t s) {
   const int* stop = &p->ctrl->status;
   T* Q = (T*)p->w_q;
-  if (op == FE_OP_CSR) return launch_spmv_t(p, rp, ci, vals, (const T*)p->w_p, Q, stop, s);
+  double* pa = p->partials;
+  if (op == FE_OP_CSR) {
+    hipLaunchKernelGGL((cg_spmv_kernel<T, SPMV_LPR>), dim3(cg_spmv_grid(p)), dim3(256), 0, s, p->n_dof, rp, ci, vals,
+                       (const T*)p->w_p, Q, stop, pa);
+    return hipGetLastError();
+  }
   ElemArgs a{};
   a.n = p->n;
   a.h = p->h;
@@ -1366,13 +1605,16 @@ static hipError_t cg_operator_t(const fe_problem* p, int op, const int32_t* rp, 
   a.tangent = p->tangent;
   a.apply_bc = 1;
   a.mat = p->mat;
+  a.sur_map = p->sur_map;
+  a.sur_D = p->sur_D;
   a.cg_r = p->w_r;
   a.cg_dinv = p->w_d;
   a.cg_pnew = cg_p_new(p, op, k);
   a.cg_pold = (a.cg_pnew == p->w_p) ? p->w_p2 : p->w_p;
   a.ctrl = p->ctrl;
-  a.partials = p->partials;
-  a.counter = p->counter;
+  a.cg_pa = pa;
+  a.cg_pu = p->partials + cg_pa_size(p);
+  a.cg_k = k;
   return launch_elem_t<T, OP_CG_APPLY>(p, a, stop, s);
 }
 
@@ -1382,17 +1624,24 @@ hipError_t cg_operator(const fe_problem* p, int op, const int32_t* rp, const int
                            : cg_operator_t(p, op, rp, ci, (const float*)vals, k, s);
 }
 
+// CSR iterations form the direction in a kernel of their own before the mat-vec.
+template <typename T> static hipError_t cg_pre_t(const fe_problem* p, int op, long k, hipStream_t s) {
+  if (op != FE_OP_CSR) return hipSuccess;
+  hipLaunchKernelGGL(cg_direction_kernel<T>, dim3(CG_UGRID), dim3(VBLOCK), 0, s, p->n_dof, (const T*)p->w_r,
+                     (const T*)p->w_d, (T*)p->w_p, p->ctrl, (const double*)(p->partials + cg_pa_size(p)), k);
+  return hipGetLastError();
+}
+
+hipError_t cg_pre(const fe_problem* p, int op, long k, hipStream_t s) {
+  return p->prec == FE_F64 ? cg_pre_t<double>(p, op, k, s) : cg_pre_t<float>(p, op, k, s);
+}
+
 template <typename T> static hipError_t cg_vectors_t(const fe_problem* p, int op, T* x, long k, hipStream_t s) {
   const int64_t n = p->n_dof;
   T* P = (T*)cg_p_new(p, op, k);
-  T* Q = (T*)p->w_q;
-  const dim3 g(vgrid(n)), b(VBLOCK);
-  if (op == FE_OP_CSR)
-    hipLaunchKernelGGL(cg_alpha_kernel<T>, g, b, 0, s, n, (const T*)P, (const T*)Q, p->ctrl, p->partials, p->counter);
-  hipLaunchKernelGGL(cg_update_kernel<T>, g, b, 0, s, n, x, (T*)p->w_r, (const T*)P, Q, (const T*)p->w_d, p->ctrl,
-                     p->partials, p->counter);
-  if (op == FE_OP_CSR)
-    hipLaunchKernelGGL(cg_direction_kernel<T>, g, b, 0, s, n, (const T*)p->w_r, (const T*)p->w_d, P, p->ctrl);
+  hipLaunchKernelGGL(cg_update_kernel<T>, dim3(CG_UGRID), dim3(VBLOCK), 0, s, n, x, (T*)p->w_r, (const T*)P,
+                     (T*)p->w_q, (const T*)p->w_d, p->ctrl, (const double*)p->partials, cg_operator_grid(p, op),
+                     p->partials + cg_pa_size(p), k);
   return hipGetLastError();
 }
 
@@ -1405,11 +1654,22 @@ template <typename T>
 __global__ void lin_stats_kernel(int64_t ne, const uint8_t* phase, Phases mat, const T* tangent,
                                  unsigned long long* out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ne || mat.ph[phase[e]].model != FE_J2) return;
-  unsigned long long pl = 0;
-  for (int q = 0; q < 8; ++q) pl += tangent[(int64_t)q * ne + e] >= T(0) ? 1 : 0;
-  atomicAdd(out, 8ull);
-  atomicAdd(out + 1, pl);
+  const bool j2 = e < ne && mat.ph[phase[e]].model == FE_J2;
+  unsigned long long cnt = 0, pl = 0;
+  if (j2) {
+    cnt = 8;
+    for (int q = 0; q < 8; ++q) pl += tangent[(int64_t)q * ne + e] >= T(0) ? 1 : 0;
+  }
+  // wave sums, one atomic per wave
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    cnt += __shfl_down(cnt, off, 64);
+    pl += __shfl_down(pl, off, 64);
+  }
+  if (__lane_id() == 0) {
+    atomicAdd(out, cnt);
+    atomicAdd(out + 1, pl);
+  }
 }
 
 hipError_t launch_lin_stats(const fe_problem* p, unsigned long long* out, hipStream_t s) {

@@ -141,11 +141,16 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(const float* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// backward pass of the mean squared error, SB samples per workgroup; weight
-// gradients are summed over workgroups with FP32 atomics (dW zeroed first).
+// backward pass of the mean squared error.  (1) per sample, the pre-activation
+// gradients delta_l = dL/dz_l of all layers go to a workspace [n][3*128+6];
+// (2) the weight gradients dWt_l[i][o] = sum_s h_{l-1}[s][i] delta_l[s][o] are
+// batch-reduced GEMMs: 32x32 tiles, the batch split into chunks of WG_K samples
+// whose partial tiles are added with FP32 atomics (dW zeroed first).
 
 constexpr int SB = 32;
 constexpr int LDB = HID + 1;
+constexpr int WSTRIDE = 3 * HID + NOUT;  // workspace row: delta1, delta2, delta3, delta4
+constexpr int WG_K = 1024;
 
 __device__ __forceinline__ double block_sum_d(double v, double* sh) {
 #pragma unroll
@@ -159,27 +164,10 @@ __device__ __forceinline__ double block_sum_d(double v, double* sh) {
   return r;
 }
 
-// Given delta (dL/dz_l, [SB][nout]) and the layer input h ([SB][nin]):
-// dWt[i][o] += sum_s h[s][i] delta[s][o], db[o] += sum_s delta[s][o].
-__device__ __forceinline__ void weight_grad(const float* h, const float* delta, int nin, int nout, int ns,
-                                            float* dWt, float* db) {
-  for (int idx = threadIdx.x; idx < nin * nout; idx += 256) {
-    const int i = idx / nout, o = idx % nout;
-    float acc = 0.0f;
-    for (int s = 0; s < ns; ++s) acc += h[s * LDB + i] * delta[s * LDB + o];
-    unsafeAtomicAdd(dWt + idx, acc);
-  }
-  for (int o = threadIdx.x; o < nout; o += 256) {
-    float acc = 0.0f;
-    for (int s = 0; s < ns; ++s) acc += delta[s * LDB + o];
-    unsafeAtomicAdd(db + o, acc);
-  }
-}
-
-// delta_prev[s][i] = silu'(z_prev[s][i]) * sum_o Wt[i][o] delta[s][o]
+// out[s][i] = silu'(zprev[s][i]) * sum_o Wt[i][o] delta[s][o]
 __device__ __forceinline__ void back_delta(const float* delta, const float* Wt, const float* zprev, int nin, int nout,
-                                           int ns, float* out) {
-  for (int idx = threadIdx.x; idx < ns * nin; idx += 256) {
+                                           float* out) {
+  for (int idx = threadIdx.x; idx < SB * nin; idx += 256) {
     const int s = idx / nin, i = idx % nin;
     float acc = 0.0f;
     for (int o = 0; o < nout; ++o) acc += Wt[i * nout + o] * delta[s * LDB + o];
@@ -187,12 +175,10 @@ __device__ __forceinline__ void back_delta(const float* delta, const float* Wt, 
   }
 }
 
-__global__ __launch_bounds__(256) void mlp_bwd_kernel(const float* __restrict__ W, const float* __restrict__ x,
-                                                      const float* __restrict__ cache, const float* __restrict__ y,
-                                                      const float* __restrict__ t, float* dW, double* loss,
-                                                      int64_t n) {
-  __shared__ float z[3][SB * LDB];   // pre-activations of the three hidden layers
-  __shared__ float hbuf[SB * LDB];   // layer input (activation or x)
+__global__ __launch_bounds__(256) void mlp_delta_kernel(const float* __restrict__ W, const float* __restrict__ cache,
+                                                        const float* __restrict__ y, const float* __restrict__ t,
+                                                        float* __restrict__ work, double* loss, int64_t n) {
+  __shared__ float z[3][SB * LDB];
   __shared__ float d0[SB * LDB], d1[SB * LDB];
   __shared__ double sh[4];
   const int64_t s0 = (int64_t)blockIdx.x * SB;
@@ -210,45 +196,84 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(const float* __restrict__ 
       const float e = y[(s0 + s) * NOUT + o] - t[(s0 + s) * NOUT + o];
       lsum += (double)e * (double)e;
       d = scale * e;
+      work[(s0 + s) * WSTRIDE + 3 * HID + o] = d;
     }
     d0[s * LDB + o] = d;
   }
-  lsum = block_sum_d(lsum, sh);
+  lsum = block_sum_d(lsum, sh);  // (synchronises the block)
   if (threadIdx.x == 0) unsafeAtomicAdd(loss, lsum / (double)n);
-  // layer 4 (input h3 = silu(z3))
-  for (int idx = threadIdx.x; idx < SB * HID; idx += 256) {
+  back_delta(d0, W + OFF_W4, z[2], HID, NOUT, d1);  // delta3
+  __syncthreads();
+  back_delta(d1, W + OFF_W3, z[1], HID, HID, d0);   // delta2
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < ns * HID; idx += 256) {
     const int s = idx / HID, c = idx % HID;
-    hbuf[s * LDB + c] = silu_f(z[2][s * LDB + c]);
+    work[(s0 + s) * WSTRIDE + 2 * HID + c] = d1[s * LDB + c];
+    work[(s0 + s) * WSTRIDE + HID + c] = d0[s * LDB + c];
   }
+  back_delta(d0, W + OFF_W2, z[0], HID, HID, d1);   // delta1
   __syncthreads();
-  weight_grad(hbuf, d0, HID, NOUT, ns, dW + OFF_W4, dW + OFF_B4);
-  back_delta(d0, W + OFF_W4, z[2], HID, NOUT, ns, d1);
-  __syncthreads();
-  // layer 3 (input h2)
-  for (int idx = threadIdx.x; idx < SB * HID; idx += 256) {
+  for (int idx = threadIdx.x; idx < ns * HID; idx += 256) {
     const int s = idx / HID, c = idx % HID;
-    hbuf[s * LDB + c] = silu_f(z[1][s * LDB + c]);
+    work[(s0 + s) * WSTRIDE + c] = d1[s * LDB + c];
   }
-  __syncthreads();
-  weight_grad(hbuf, d1, HID, HID, ns, dW + OFF_W3, dW + OFF_B3);
-  back_delta(d1, W + OFF_W3, z[1], HID, HID, ns, d0);
-  __syncthreads();
-  // layer 2 (input h1)
-  for (int idx = threadIdx.x; idx < SB * HID; idx += 256) {
-    const int s = idx / HID, c = idx % HID;
-    hbuf[s * LDB + c] = silu_f(z[0][s * LDB + c]);
+}
+
+// Weight-gradient tiles: blockIdx.y enumerates (layer, input tile, output tile), 40 in all;
+// blockIdx.x the batch chunk.
+__global__ __launch_bounds__(256) void mlp_wgrad_kernel(const float* __restrict__ x, const float* __restrict__ cache,
+                                                        const float* __restrict__ work, float* dW, int64_t n) {
+  __shared__ float hs[32][33], ds[32][33];
+  const int tile = blockIdx.y;
+  int layer, it, ot;
+  if (tile < 4) {
+    layer = 0; it = 0; ot = tile;
+  } else if (tile < 20) {
+    layer = 1; it = (tile - 4) / 4; ot = (tile - 4) % 4;
+  } else if (tile < 36) {
+    layer = 2; it = (tile - 20) / 4; ot = (tile - 20) % 4;
+  } else {
+    layer = 3; it = tile - 36; ot = 0;
   }
-  __syncthreads();
-  weight_grad(hbuf, d0, HID, HID, ns, dW + OFF_W2, dW + OFF_B2);
-  back_delta(d0, W + OFF_W2, z[0], HID, HID, ns, d1);
-  __syncthreads();
-  // layer 1 (input x)
-  for (int idx = threadIdx.x; idx < SB * NIN; idx += 256) {
-    const int s = idx / NIN, c = idx % NIN;
-    hbuf[s * LDB + c] = s < ns ? x[(s0 + s) * NIN + c] : 0.0f;
+  const int nin = layer == 0 ? NIN : HID, nout = layer == 3 ? NOUT : HID;
+  const int woff = layer == 0 ? OFF_W1 : (layer == 1 ? OFF_W2 : (layer == 2 ? OFF_W3 : OFF_W4));
+  const int boff = layer == 0 ? OFF_B1 : (layer == 1 ? OFF_B2 : (layer == 2 ? OFF_B3 : OFF_B4));
+  const int doff = layer * HID;  // delta_{layer+1} column offset in the workspace
+  const int64_t k0 = (int64_t)blockIdx.x * WG_K, k1 = min<int64_t>(n, k0 + WG_K);
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads, 4 outputs each
+  float acc[4] = {0.f, 0.f, 0.f, 0.f}, bacc = 0.f;
+  for (int64_t sb = k0; sb < k1; sb += 32) {
+    for (int idx = threadIdx.x; idx < 32 * 32; idx += 256) {
+      const int s = idx / 32, c = idx % 32;
+      const int64_t gs = sb + s;
+      const int i = it * 32 + c, o = ot * 32 + c;
+      float hv = 0.f, dv = 0.f;
+      if (gs < k1) {
+        if (i < nin) hv = layer == 0 ? x[gs * NIN + i] : silu_f(cache[gs * 3 * HID + (layer - 1) * HID + i]);
+        if (o < nout) dv = work[gs * WSTRIDE + doff + o];
+      }
+      hs[s][c] = hv;
+      ds[s][c] = dv;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int s = 0; s < 32; ++s) {
+      const float dv = ds[s][tx];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] += hs[s][ty * 4 + r] * dv;
+      if (it == 0 && ty == 0) bacc += dv;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  weight_grad(hbuf, d1, NIN, HID, ns, dW + OFF_W1, dW + OFF_B1);
+  const int o = ot * 32 + tx;
+  if (o < nout) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = it * 32 + ty * 4 + r;
+      if (i < nin) unsafeAtomicAdd(dW + woff + i * nout + o, acc[r]);
+    }
+    if (it == 0 && ty == 0) unsafeAtomicAdd(dW + boff + o, bacc);
+  }
 }
 
 __global__ void adam_kernel(float* W, const float* dW, float* m, float* v, int64_t np, float lr, float b1, float b2,
@@ -298,15 +323,17 @@ extern "C" int fe_mlp_forward(const float* W, const float* x, float* y, float* j
 }
 
 extern "C" int fe_mlp_backward(const float* W, const float* x, const float* cache, const float* y, const float* target,
-                               float* dW, double* loss, int64_t n, void* stream) {
-  if (!W || !x || !cache || !y || !target || !dW || !loss || n <= 0) {
+                               float* dW, double* loss, float* work, int64_t n, void* stream) {
+  if (!W || !x || !cache || !y || !target || !dW || !loss || !work || n <= 0) {
     set_error("fe_mlp_backward: all arrays are required, n > 0");
     return FE_ERR_ARG;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(zero_kernel, dim3(64), dim3(256), 0, s, dW, (int64_t)FE_MLP_PARAMS, loss);
-  hipLaunchKernelGGL(mlp_bwd_kernel, dim3((unsigned)((n + SB - 1) / SB)), dim3(256), 0, s, W, x, cache, y, target,
-                     dW, loss, n);
+  hipLaunchKernelGGL(mlp_delta_kernel, dim3((unsigned)((n + SB - 1) / SB)), dim3(256), 0, s, W, cache, y, target,
+                     work, loss, n);
+  hipLaunchKernelGGL(mlp_wgrad_kernel, dim3((unsigned)((n + WG_K - 1) / WG_K), 40), dim3(256), 0, s, x, cache, work,
+                     dW, n);
   HIPCHK(hipGetLastError());
   return FE_OK;
 }

@@ -68,7 +68,10 @@ SIGNATURES = [
     ("fe_profile_read", _i32, [_vp, ctypes.POINTER(_dbl)]),
     ("fe_linearization_stats", _i32, [_vp, ctypes.POINTER(_i64), _vp]),
     ("fe_mlp_forward", _i32, [_vp, _vp, _vp, _vp, _vp, _i64, _vp]),
-    ("fe_mlp_backward", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp]),
+    ("fe_mlp_backward", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp]),
+    ("fe_set_surrogate", _i32, [_vp, _vp, _dbl]),
+    ("fe_surrogate_stats", _i32, [_vp, ctypes.POINTER(_i64), _vp]),
+    ("fe_set_capture", _i32, [_vp, _vp, _vp, _i64, _vp, _i32]),
     ("fe_adam_step", _i32, [_vp, _vp, _vp, _vp, _i64, _dbl, _dbl, _dbl, _dbl, _i32, _vp]),
     ("fe_status_string", ctypes.c_char_p, [_i32]),
     ("fe_last_error", ctypes.c_char_p, []),
@@ -297,6 +300,25 @@ class Problem:
         return {k: (int(out[3 * i]), float(out[3 * i + 1]), float(out[3 * i + 2]))
                 for i, k in enumerate(self.KERNEL_CLASSES)}
 
+    def set_surrogate(self, W, fallback_tol=1e-3):
+        """Use the network (float32 [35590] device tensor, kept alive by the caller) at plastic-trial J2 points."""
+        if W is not None:
+            _f32(W, MLP_PARAMS, "W")
+        self._sur_W = W
+        _check(self.lib.fe_set_surrogate(self.handle, _ptr(W), float(fallback_tol)), "fe_set_surrogate")
+
+    def surrogate_stats(self):
+        out = (_i64 * 3)()
+        _check(self.lib.fe_surrogate_stats(self.handle, out, _stream()), "fe_surrogate_stats")
+        return dict(listed=int(out[0]), accepted=int(out[1]), fallback=int(out[2]))
+
+    def set_capture(self, x=None, y=None, count=None, stride=1):
+        """Append (normalised input, exact stress) samples at plastic-trial J2 points on every residual."""
+        cap = 0 if x is None else x.shape[0]
+        self._capture = (x, y, count)
+        _check(self.lib.fe_set_capture(self.handle, _ptr(x), _ptr(y), cap, _ptr(count), int(stride)),
+               "fe_set_capture")
+
     def linearization_stats(self):
         out = (_i64 * 2)()
         _check(self.lib.fe_linearization_stats(self.handle, out, _stream()), "fe_linearization_stats")
@@ -334,8 +356,9 @@ def mlp_backward(W, x, cache, y, target):
     n = x.shape[0]
     dW = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
     loss = torch.empty(1, dtype=torch.float64, device=x.device)
-    _check(lib.fe_mlp_backward(_ptr(W), _ptr(x), _ptr(cache), _ptr(y), _ptr(target), _ptr(dW), _ptr(loss), n,
-                               _stream()), "fe_mlp_backward")
+    work = torch.empty(n, 3 * MLP_HIDDEN + MLP_OUT, dtype=torch.float32, device=x.device)
+    _check(lib.fe_mlp_backward(_ptr(W), _ptr(x), _ptr(cache), _ptr(y), _ptr(target), _ptr(dW), _ptr(loss),
+                               _ptr(work), n, _stream()), "fe_mlp_backward")
     return dW, loss
 
 

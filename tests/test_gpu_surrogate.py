@@ -1,0 +1,132 @@
+"""GPU surrogate path against the oracle.
+
+* capture: the number of recorded samples equals the oracle's count of
+  plastic-trial J2 points (bit-exact integer), and every recorded (input, stress)
+  pair satisfies the oracle's return map on the decoded input;
+* consume: with a network trained by the library kernels, the trial state
+  written by the GPU residual matches the oracle's surrogate update (FP64
+  network on the same FP32 weights) at every point where both sides take the
+  same accept/fallback decision; decisions may differ only where the local
+  check sits within FP32 rounding of the threshold (bounded at 1%).
+Training quality itself is not pinned (stochastic); the test only needs a
+network good enough that some points pass the local check.
+"""
+import numpy as np
+import pytest
+
+from helpers import PHASES_J2_FIBER, lib_materials, oracle_phases, state_from_lib, state_to_lib
+from oracle import element, j2, mlp, surrogate as osur
+from oracle.rve import RVE
+from paper_2604_22087_amd import inputs
+
+pytestmark = pytest.mark.gpu
+E, NU, SY, H = 3.5, 0.35, 0.05, 0.1
+S_IN, S_OUT = SY / E, SY
+
+
+def _setup(n, seed=11):
+    import torch
+    from paper_2604_22087_amd import fe
+    phase = inputs.fiber_phase(n, n_fibers=4, radius=0.18, seed=2)
+    rve = RVE(n, phase, oracle_phases(PHASES_J2_FIBER))
+    amp = 0.012 / n
+    u = rve.affine_lift(np.diag([0.03, -0.01, 0.0])) + inputs.random_displacement(n, -amp, amp, seed=7)
+    rng = np.random.default_rng(seed)
+    st = rve.zero_state()
+    ep = rng.normal(scale=2e-3, size=st["eps_p"].shape)
+    ep[..., 2] = -ep[..., 0] - ep[..., 1]
+    st["eps_p"] = ep * (rve.phase == 0)[:, None, None]
+    st["alpha"] = rng.uniform(0, 2e-3, st["alpha"].shape) * (rve.phase == 0)[:, None]
+    P = fe.Problem(n, "f64")
+    models, params = lib_materials(PHASES_J2_FIBER)
+    P.set_materials(torch.tensor(phase, device="cuda"), models, params)
+    return rve, u, st, P
+
+
+def _decode(x):
+    x = np.asarray(x, dtype=np.float64)
+    eps_tr = x[:, :6] * S_IN * osur.SHEAR
+    epn = x[:, 6:12] * S_IN * osur.SHEAR
+    return eps_tr + epn, epn, x[:, 12] * S_IN
+
+
+def test_capture_matches_return_map():
+    import torch
+    n = 6
+    rve, u, st, P = _setup(n)
+    _, _, trial = rve.element_residual_tangent(u, st)
+    n_ref = int(trial["plastic"].sum())
+    cap = 8 * n ** 3
+    x = torch.empty(cap, 13, dtype=torch.float32, device="cuda")
+    y = torch.empty(cap, 6, dtype=torch.float32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    P.set_capture(x, y, count, stride=1)
+    P.residual(torch.tensor(u, device="cuda"), torch.tensor(state_to_lib(st["eps_p"], st["alpha"]), device="cuda"))
+    P.set_capture(None)
+    m = int(count.item())
+    assert m == n_ref
+    eps, epn, an = _decode(x[:m].cpu().numpy())
+    rm = j2.return_map(eps, epn, an, E, NU, SY, H)
+    assert rm["plastic"].all()
+    y_ref = osur.stress_voigt_to_mandel(rm["sigma"]) / S_OUT
+    err = np.abs(y[:m].double().cpu().numpy() - y_ref).max() / np.abs(y_ref).max()
+    assert err < 1e-5  # float32 storage of inputs and outputs
+
+
+def test_surrogate_consume_matches_oracle():
+    import torch
+    from paper_2604_22087_amd import fe
+    from paper_2604_22087_amd import surrogate as gsur
+    n = 6
+    rve, u, st, P = _setup(n)
+    # training data: captured from a few residual evaluations around the test state
+    xs, ys = [], []
+    cap = 8 * n ** 3
+    for k, s in enumerate((0.6, 0.8, 1.0, 1.2, 1.4)):
+        x = torch.empty(cap, 13, dtype=torch.float32, device="cuda")
+        y = torch.empty(cap, 6, dtype=torch.float32, device="cuda")
+        count = torch.zeros(1, dtype=torch.int32, device="cuda")
+        P.set_capture(x, y, count, stride=1)
+        P.residual(torch.tensor(s * u, device="cuda"),
+                   torch.tensor(state_to_lib(st["eps_p"], st["alpha"]), device="cuda"))
+        P.set_capture(None)
+        m = int(count.item())
+        xs.append(x[:m])
+        ys.append(y[:m])
+    X, Y = torch.cat(xs).contiguous(), torch.cat(ys).contiguous()
+    W, hist = gsur.train(X, Y, epochs=60, batch=512, lr=3e-3)
+    assert hist[-1]["val_loss"] < hist[0]["val_loss"]
+    tol = 0.05
+    P.set_surrogate(W, fallback_tol=tol)
+    s_in = torch.tensor(state_to_lib(st["eps_p"], st["alpha"]), device="cuda")
+    s_out = P.state()
+    P.residual(torch.tensor(u, device="cuda"), s_in, s_out)
+    stats = P.surrogate_stats()
+    print(f"  surrogate stats {stats}", flush=True)
+    assert stats["accepted"] > 0
+    # oracle: same points, FP64 network on the same weights
+    flat = W.double().cpu().numpy()
+    params, off = [], 0
+    for fi, fo in zip(mlp.LAYERS[:-1], mlp.LAYERS[1:]):
+        Wt = flat[off:off + fi * fo].reshape(fi, fo)
+        off += fi * fo
+        params.append((Wt.T, flat[off:off + fo]))
+        off += fo
+
+    def net(xx):
+        return mlp.forward(params, xx)[0], mlp.jacobian(params, xx)
+
+    eps_q = element.qp_strains(rve.coords, rve.conn, u)
+    ep_g, al_g = state_from_lib(s_out.cpu().numpy(), n ** 3)
+    agree, flips, used_tot = 0, 0, 0
+    for q in range(8):
+        sel = rve.phase == 0
+        out = osur.update(eps_q[q][sel], st["eps_p"][sel, q], st["alpha"][sel, q], E, NU, SY, H, net, S_IN, S_OUT, tol)
+        used_tot += int(out["used"].sum())
+        a_ref, a_gpu = out["alpha"], al_g[sel, q]
+        close = np.abs(a_gpu - a_ref) <= 1e-5 * np.maximum(np.abs(a_ref), 1e-3)
+        agree += int(close.sum())
+        flips += int((~close).sum())
+        assert np.abs(ep_g[sel, q][close] - out["eps_p"][close]).max() <= 1e-6
+    assert abs(used_tot - stats["accepted"]) <= 0.01 * stats["listed"] + 1
+    assert flips <= 0.01 * stats["listed"] + 1
