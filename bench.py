@@ -62,6 +62,94 @@ def run_ramp(P, u, state, path):
                     newton_rtol=1e-8 if f64 else 1e-5, pcg_rtol=1e-10 if f64 else 1e-6, max_newton=30)
 
 
+def operator_rates(P, u, state, reps=50):
+    """K*u rates at the current linearisation: matrix-free and assembled CSR, each hot (back to back,
+    as inside PCG) and cold (a 1 GiB write before every launch evicts the 256 MB last-level cache).
+    Times are the library's own HIP events around each launch; bytes are algorithmic."""
+    import torch
+    from paper_2604_22087_amd import fe
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn(P.n_dof, dtype=P.dtype, device="cuda", generator=g)
+    y = P.vector()
+    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    rp, ci = P.csr_indices()
+    vals = P.tangent_csr(u, state, apply_bc=True)
+    P.residual(u, state, P.state(), apply_bc=True, store_tangent=True)  # matrix-free linearisation = CSR's
+    out = {}
+    calls = (("matfree", "matfree_apply", lambda: P.apply_matfree(x, y, apply_bc=True)),
+             ("csr", "csr_spmv", lambda: P.apply_csr(rp, ci, vals, x, y)))
+    for name, key, call in calls:
+        for mode in ("hot", "cold"):
+            for _ in range(5):
+                call()
+            torch.cuda.synchronize()
+            P.profile(True)
+            for k in range(reps):
+                if mode == "cold":
+                    flush.fill_(float(k))
+                call()
+            c, ms, by = P.profile_read()[key]
+            P.profile(False)
+            t = ms / c * 1e-3
+            out[f"{name}_{mode}"] = {"us": 1e6 * t, "gdofs": P.n_dof / t / 1e9, "GBs": by / c / t / 1e9,
+                                     "frac": by / c / t / 1e9 / HBM_PEAK_GBS, "bytes": by / c}
+    del vals, flush
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(20):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    out["copy_GBs"] = 20 * 2 * a.numel() * 8 / (s.elapsed_time(e) * 1e-3) / 1e9
+    return out
+
+
+def neohooke_leg(n):
+    """Finite-strain leg: n^3 compressible Neo-Hookean RVE with a log-normal shear-modulus field
+    (mean 1, CoV 0.5, correlation length 0.1, seed 3; lambda_e = 1.5 mu_e), F_xx -> 1.1 in 5 load
+    steps, matrix-free Jacobi-PCG.  Run in FP32 (element kernels and K*u in FP32, PCG scalars and
+    Newton norms in FP64) and in FP64; reports times, K*u rates and the FP32 error against FP64."""
+    import torch
+    from paper_2604_22087_amd import fe, inputs
+    mu = inputs.lognormal_field(n, seed=3)
+    path = [np.diag([0.02 * k, 0.0, 0.0]) for k in range(1, 6)]
+    res, sol = {}, {}
+    for prec in ("f32", "f64"):
+        P = fe.Problem(n, prec)
+        P.set_materials(torch.zeros(n ** 3, dtype=torch.uint8, device="cuda"), [fe.NEOHOOKE],
+                        [(2.6, 0.3, 0.0, 0.0)], torch.tensor(mu, dtype=P.dtype, device="cuda"))
+        P.set_dirichlet(torch.tensor(inputs.boundary_dof_mask(n), device="cuda"))
+        u, state = P.vector(), P.state()
+        f64 = prec == "f64"
+        torch.cuda.synchronize()
+        P.profile(True)
+        t0 = time.perf_counter()
+        _, _, sig, info = P.newton(path, u=u, state=state, op=fe.OP_MATFREE, newton_rtol=1e-8 if f64 else 1e-5,
+                                   pcg_rtol=1e-10 if f64 else 1e-6, max_newton=30)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        c, ms, by = P.profile_read()["matfree_apply"]
+        P.profile(False)
+        t = ms / max(c, 1) * 1e-3
+        res[prec] = {"seconds": dt, "newton_iterations": info["newton_iterations"],
+                     "pcg_iterations": info["pcg_iterations"], "ku_applies": info["operator_applies"],
+                     "ku_us": 1e6 * t, "ku_gdofs": P.n_dof / t / 1e9, "ku_GBs": by / max(c, 1) / t / 1e9,
+                     "ku_frac_hbm": by / max(c, 1) / t / 1e9 / HBM_PEAK_GBS,
+                     "whole_ramp_gdofs": P.n_dof * info["operator_applies"] / dt / 1e9}
+        sol[prec] = (u.double(), np.array(sig))
+        del P
+    (u32, s32), (u64, s64) = sol["f32"], sol["f64"]
+    res["f32_vs_f64"] = {"u_rel_err": float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64)),
+                         "stress_bar_max_rel_err": float(np.max(np.abs(s32 - s64)) / np.max(np.abs(s64)))}
+    res["workload"] = (f"{n}^3 compressible Neo-Hookean, log-normal mu (mean 1, CoV 0.5, l = 0.1), "
+                       f"lambda = 1.5 mu, F_xx -> 1.1 in 5 steps, matrix-free Jacobi-PCG")
+    return res
+
+
 def cpu_baseline(n, phase, gpu_info, path):
     """The FP64 oracle on a bounded sample of the same workload (host cores)."""
     from oracle import solver
@@ -100,6 +188,7 @@ def main():
     ap.add_argument("--load-steps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 ramp")
+    ap.add_argument("--nh", type=int, default=0, help="also run the finite-strain Neo-Hookean leg at this n (0: skip)")
     ap.add_argument("--copy-calib", action="store_true", help="run only a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -165,6 +254,7 @@ def main():
         "ku_applies": infos[-1]["operator_applies"],
         "sigma_bar_xx_last": sig[-1][0],
     }
+    out["operators_f64"] = operator_rates(P, u, state)
     if not args.no_fp32:
         P32, _ = setup(n, "f32")
         u32, s32 = P32.vector(), P32.state()
@@ -179,8 +269,12 @@ def main():
         out["fp32"] = {"value": P32.n_dof * info32["operator_applies"] / t32 / 1e9, "ms_per_step": 1e3 * t32,
                        "sigma_bar_xx_max_rel_err_vs_f64": float(np.max(np.abs(s32a - s64) / np.abs(s64))),
                        "u_rel_err_vs_f64": float(torch.linalg.norm(u32.double() - u) / torch.linalg.norm(u)),
-                       "pcg_iterations": info32["pcg_iterations"]}
+                       "pcg_iterations": info32["pcg_iterations"],
+                       "operators": operator_rates(P32, u32, s32)}
         del P32
+    if args.nh:
+        print(f"[bench] neo-hookean leg {args.nh}^3", file=sys.stderr, flush=True)
+        out["neohooke"] = neohooke_leg(args.nh)
     if not args.no_cpu:
         print("[bench] cpu oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(n, phase, infos[-1], path)
