@@ -170,3 +170,59 @@ def test_config1_bounds_and_hill_mandel():
         assert reuss < capp < voigt
         sbar = rve.mean_stress(trial["sigma_all"])
         assert energy == pytest.approx(sbar[0] * exx, rel=1e-9)
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_node_blocks_equal_dense_blocks(n):
+    """Node blocks of the element-by-element operator = 3x3 diagonal blocks read off
+    the assembled, Dirichlet-eliminated dense matrix."""
+    coords, conn, k = _two_phase_tangents(n, seed=3)
+    ndof = 3 * len(coords)
+    mask = inputs.boundary_dof_mask(n)
+    rp, ci, v = assembly.assemble_csr(conn, k, ndof)
+    vb = assembly.dirichlet_csr(rp, ci, v, mask)
+    dense = np.zeros((ndof, ndof))
+    dense[assembly.csr_rows(rp), ci] = vb
+    blocks = solver.matfree_node_blocks(conn, k, ndof, mask)
+    for a in range(len(coords)):
+        assert np.abs(blocks[a] - dense[3 * a:3 * a + 3, 3 * a:3 * a + 3]).max() <= 1e-14 * np.abs(dense).max()
+
+
+def test_block_jacobi_pcg_special_cases():
+    """(i) a block-diagonal SPD matrix is solved exactly in one iteration;
+    (ii) with diagonal blocks the iterates equal point-Jacobi PCG;
+    (iii) on the config-1 problem it converges to the dense solution."""
+    rng = np.random.default_rng(5)
+    nb = 7
+    g = rng.normal(size=(nb, 3, 3))
+    blocks = np.einsum("nij,nkj->nik", g, g) + 3 * np.eye(3)
+    dense = np.zeros((3 * nb, 3 * nb))
+    for a in range(nb):
+        dense[3 * a:3 * a + 3, 3 * a:3 * a + 3] = blocks[a]
+    b = rng.normal(size=3 * nb)
+    x, it, status, rel = solver.pcg(lambda p: dense @ p, None, b, 1e-14, 10, precond=solver.block_jacobi(blocks))
+    assert status == solver.OK and it == 1 and rel <= 1e-14
+    spd = rng.normal(size=(3 * nb, 3 * nb))
+    spd = spd @ spd.T + 3 * nb * np.eye(3 * nb)
+    dg = np.diag(spd).copy()
+    diag_blocks = np.zeros((nb, 3, 3))
+    for a in range(nb):
+        diag_blocks[a] = np.diag(dg[3 * a:3 * a + 3])
+    for max_it in (1, 2, 5):
+        x1, _, _, _ = solver.pcg(lambda p: spd @ p, dg, b, 1e-30, max_it)
+        x2, _, _, _ = solver.pcg(lambda p: spd @ p, None, b, 1e-30, max_it, precond=solver.block_jacobi(diag_blocks))
+        assert np.abs(x1 - x2).max() <= 1e-13 * np.abs(x1).max()
+    n = 3
+    coords, conn, k = _two_phase_tangents(n, seed=11)
+    ndof = 3 * len(coords)
+    mask = inputs.boundary_dof_mask(n)
+    rp, ci, v = assembly.assemble_csr(conn, k, ndof)
+    vb = assembly.dirichlet_csr(rp, ci, v, mask)
+    dense = np.zeros((ndof, ndof))
+    dense[assembly.csr_rows(rp), ci] = vb
+    b = RNG.normal(size=ndof) * (1 - mask)
+    x_ref = np.linalg.solve(dense, b)
+    pre = solver.block_jacobi(solver.matfree_node_blocks(conn, k, ndof, mask))
+    x, it, status, rel = solver.pcg(lambda p: solver.matfree_apply(conn, k, p, mask), None, b, 1e-14, 1000, precond=pre)
+    assert status == solver.OK and rel <= 1e-13
+    assert np.linalg.norm(x - x_ref) <= 1e-12 * np.linalg.norm(x_ref)
