@@ -60,6 +60,7 @@ typedef enum {
 enum { FE_F64 = 0, FE_F32 = 1 };                      /* precision of real arrays */
 enum { FE_LINEAR = 0, FE_J2 = 1, FE_NEOHOOKE = 2 };    /* constitutive model per phase */
 enum { FE_OP_CSR = 0, FE_OP_MATFREE = 1 };             /* operator used by fe_pcg / fe_newton */
+enum { FE_PC_JACOBI = 0, FE_PC_BLOCK_JACOBI = 1 };     /* CG preconditioner (fe_set_preconditioner) */
 enum { FE_APPLY_BC = 1, FE_STORE_TANGENT = 2 };        /* fe_residual flags */
 enum { FE_MAX_PHASES = 8 };
 
@@ -153,7 +154,19 @@ int fe_apply_csr(fe_problem* p, const int32_t* row_ptr, const int32_t* col_idx, 
 /* Diagonal of the (masked, if apply_bc) matrix-free operator: d real [n_dof]. */
 int fe_diagonal(fe_problem* p, void* d, int apply_bc, void* stream);
 
-/* Jacobi-preconditioned CG on A x = b (Fig. 4): A is the masked operator
+/* Preconditioner of fe_pcg and fe_newton's inner solves (default FE_PC_JACOBI).
+ * FE_PC_JACOBI: M = diag(A) (Fig. 4).  FE_PC_BLOCK_JACOBI: M = the 3x3 blocks of
+ * A that couple the three components of one node, the first step towards the
+ * stronger preconditioning of the assembled matrix compared in Fig. 7; taken
+ * from the CSR values with FE_OP_CSR (and with fe_newton's assemble_csr), from
+ * the stored linearisation otherwise.  The blocks are inverted once per solve
+ * (workspace of 6 reals per node, allocated on first use; FE_ERR_OOM if that
+ * fails).  A block with determinant <= 0 sets bit 1 of fe_read_flags; a
+ * singular one makes the solve end with FE_ERR_NONFINITE.  FE_ERR_ARG for any
+ * other kind. */
+int fe_set_preconditioner(fe_problem* p, int kind);
+
+/* Preconditioned CG on A x = b (Fig. 4): A is the masked operator
  * P_f K P_f + P_b, matrix-free (op = FE_OP_MATFREE, CSR arguments ignored) or the
  * CSR matrix given (op = FE_OP_CSR, already eliminated).  x0 = 0; stops when
  * ||r||_2 <= rtol ||b||_2.  x: real [n_dof] output.  info_host may be NULL.
@@ -204,7 +217,8 @@ int fe_profile_read(fe_problem* p, double* out_host);
 int fe_linearization_stats(fe_problem* p, int64_t* out_host, void* stream);
 
 /* Device-side error flags raised by element kernels since the last read
- * (bit 0: inverted element).  Synchronises and clears. */
+ * (bit 0: inverted element; bit 1: a node block of the block-Jacobi
+ * preconditioner with determinant <= 0).  Synchronises and clears. */
 int fe_read_flags(fe_problem* p, int* flags_host, void* stream);
 
 /* ---- learned constitutive surrogate (Sec. III-B: a surrogate may replace the

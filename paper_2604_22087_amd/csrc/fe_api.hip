@@ -121,6 +121,7 @@ void fe_problem_destroy(fe_problem* p) {
   free_dev(p->w_p2);
   free_dev(p->w_q);
   free_dev(p->w_d);
+  free_dev(p->w_blk);
   free_dev(p->w_v);
   free_dev(p->w_v2);
   free_dev(p->w_state);
@@ -470,6 +471,16 @@ int fe_diagonal(fe_problem* p, void* d, int apply_bc, void* stream) {
   return FE_OK;
 }
 
+int fe_set_preconditioner(fe_problem* p, int kind) {
+  CHKP(p);
+  if (kind != FE_PC_JACOBI && kind != FE_PC_BLOCK_JACOBI) return arg_error("kind must be FE_PC_JACOBI or FE_PC_BLOCK_JACOBI");
+  if (kind == FE_PC_BLOCK_JACOBI && !p->w_blk) {
+    if (int st = alloc(&p->w_blk, 6 * real_size(p) * (size_t)p->n_nodes)) return st;
+  }
+  p->precond = kind;
+  return FE_OK;
+}
+
 }  // extern "C"
 
 // CG driver: kernels run with device-side scalars; the host checks the status
@@ -478,7 +489,9 @@ int fe_diagonal(fe_problem* p, void* d, int apply_bc, void* stream) {
 // else from the element kernel; `op` selects the operator inside the iteration.
 static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, const void* b,
                    void* x, double rtol, int max_it, fe_pcg_info* info, hipStream_t s, int* applies) {
-  if (rp) {
+  if (p->precond == FE_PC_BLOCK_JACOBI) {
+    HIPCHK(launch_block_jacobi(p, rp, ci, vals, p->w_blk, s));
+  } else if (rp) {
     HIPCHK(launch_csr_diag(p, rp, ci, vals, p->w_d, s));
   } else {
     HIPCHK(launch_diag(p, p->w_d, 1, s));
@@ -508,8 +521,10 @@ static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, 
     if (p->prof_recs.size() > rec0 + executed) p->prof_recs.resize(rec0 + executed);
     double b = 0;
     if (int e = operator_bytes(p, op, s, &b)) return e;
-    // the fused matrix-free CG operator reads r, M^-1, p_old and writes p instead of reading x
-    if (op == FE_OP_MATFREE) b += 3.0 * (double)real_size(p) * (double)p->n_dof;
+    // the fused matrix-free CG operator reads r, M^-1 (1 or 2 reals per dof), p_old and
+    // writes p instead of reading x
+    if (op == FE_OP_MATFREE)
+      b += (p->precond == FE_PC_BLOCK_JACOBI ? 4.0 : 3.0) * (double)real_size(p) * (double)p->n_dof;
     p->prof_bytes[cls] += b * (double)executed;
   }
   if (info) {

@@ -96,7 +96,8 @@ struct ElemArgs {
   unsigned int sur_stride, sur_salt;
   // OP_CG_APPLY only
   const void* cg_r;       // residual r
-  const void* cg_dinv;    // inverse Jacobi diagonal
+  const void* cg_dinv;    // preconditioner: inverse diagonal [n_dof] or inverse node blocks [n_nodes][6]
+  int cg_block;           // 1: node-block Jacobi
   const void* cg_pold;    // previous search direction
   void* cg_pnew;          // new search direction (written)
   CgCtrl* ctrl;
@@ -130,6 +131,8 @@ struct fe_problem {
   void* w_p2 = nullptr;       // second search-direction buffer (fused matrix-free CG)
   void* w_q = nullptr;
   void* w_d = nullptr;        // inverse diagonal
+  int precond = FE_PC_JACOBI; // FE_PC_JACOBI or FE_PC_BLOCK_JACOBI
+  void* w_blk = nullptr;      // inverse node blocks [n_nodes][6] (allocated on first use)
   void* w_v = nullptr;        // scratch vector (Newton)
   void* w_v2 = nullptr;       // scratch vector (Newton)
   void* w_state = nullptr;    // J2 trial state (Newton)
@@ -190,6 +193,11 @@ hipError_t launch_dot(const fe_problem* p, const void* a, const void* b, int64_t
 hipError_t launch_csr_diag(const fe_problem* p, const int32_t* rp, const int32_t* ci, const void* v, void* d,
                            hipStream_t s);
 hipError_t launch_copy_cvt(const fe_problem* p, const void* src, void* dst, int64_t n, hipStream_t s);
+// inverse node blocks of the CSR matrix (rp != null) or of the matrix-free operator, Dirichlet-eliminated
+hipError_t launch_block_jacobi(const fe_problem* p, const int32_t* rp, const int32_t* ci, const void* v, void* blk,
+                               hipStream_t s);
+// buffer the CG kernels read M^-1 from
+inline void* pc_buffer(const fe_problem* p) { return p->precond == FE_PC_BLOCK_JACOBI ? p->w_blk : p->w_d; }
 
 hipError_t launch_lin_stats(const fe_problem* p, unsigned long long* out, hipStream_t s);
 // network forward + Jacobian over a device-counted list (blocks beyond *count return)

@@ -134,6 +134,22 @@ __device__ __forceinline__ bool cg_direction_step(CgCtrl* ctrl, const double* pu
   return st == CG_RUNNING;
 }
 
+// (M^-1 r)[dof]: point Jacobi (M holds 1/diag, [n_dof]) or node-block Jacobi (M holds the
+// symmetric 3x3 inverse blocks [n_nodes][6], order xx yy zz yz xz xy).  Every caller forms
+// the same expression, so a node's value does not depend on who computes it.
+template <typename T>
+__device__ __forceinline__ T pc_apply(const T* M, const T* R, int64_t dof, int block) {
+  if (!block) return M[dof] * R[dof];
+  const int64_t nd = dof / 3;
+  const int c = (int)(dof - 3 * nd);
+  const T* m = M + 6 * nd;
+  const T* r = R + 3 * nd;
+  const T m0 = c == 0 ? m[0] : (c == 1 ? m[5] : m[4]);
+  const T m1 = c == 0 ? m[5] : (c == 1 ? m[1] : m[3]);
+  const T m2 = c == 0 ? m[4] : (c == 1 ? m[3] : m[2]);
+  return m0 * r[0] + m1 * r[1] + m2 * r[2];
+}
+
 // G[r][q] = sum_{k,j} M[r][k] M[q][j] D[k][j] with M = [[GA,GB],[GB,GA]] (M symmetric,
 // so the same map also pushes Gauss-point values back to the nodes).
 template <typename T> __device__ __forceinline__ void interp2(const T D[2][2], T G[2][2]) {
@@ -548,7 +564,7 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
       const int64_t dof = 3 * (gi + np1 * (gj + np1 * gk)) + c;
       if (OP == OP_CG_APPLY) {
         // new search direction, formed identically by every brick that touches the node
-        v = CD[dof] * CR[dof] + cg_beta * CP[dof];
+        v = pc_apply(CD, CR, dof, a.cg_block) + cg_beta * CP[dof];
         if ((min(gi, n - 1) - a0 < TX) && (min(gj, n - 1) - b0 < TY) && (min(gk, n - 1) - c0 < TZ)) CPN[dof] = v;
       } else {
         v = X[dof];
@@ -867,7 +883,7 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
     if (a.apply_bc && a.mask && a.mask[dof]) {
       if (own) {
         if (OP == OP_CG_APPLY) {  // A p = p on constrained dofs; their p.Ap share is p^2
-          const T v = CD[dof] * CR[dof] + cg_beta * CP[dof];
+          const T v = pc_apply(CD, CR, dof, a.cg_block) + cg_beta * CP[dof];
           Y[dof] = v;
           pq += (double)v * (double)v;
         } else {
@@ -1332,6 +1348,128 @@ hipError_t launch_csr_diag(const fe_problem* p, const int32_t* rp, const int32_t
 }
 
 // ---------------------------------------------------------------------------
+// Node-block Jacobi: the 3x3 blocks of A on the diagonal, one per node, stored
+// as 6 symmetric entries [n_nodes][6] in the order xx yy zz yz xz xy.
+
+// Blocks of the matrix-free operator: one lane per element, 8 x 6 entries added atomically (blk zeroed before).
+template <typename T, int MS>
+__global__ __launch_bounds__(256) void block_diag_kernel(TanArgs a, T* blk) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= a.n_el) return;
+  const int n = a.n;
+  const int ea = (int)(e % n), eb = (int)((e / n) % n), ec = (int)(e / ((int64_t)n * n));
+  const T inv_h = T(1.0 / a.h), w = T(0.125 * a.h * a.h * a.h);
+  T acc[8][6] = {};
+  for (int qp = 0; qp < 8; ++qp) {
+    const int p = qp & 1, q = (qp >> 1) & 1, r = qp >> 2;
+    QpTangent<T> t;
+    load_qp_tangent<T, MS>(a, e, qp, t);
+#pragma unroll
+    for (int l = 0; l < 8; ++l) {
+      T g[3], B[3][3] = {};
+      basis_grad(l & 1, (l >> 1) & 1, l >> 2, p, q, r, inv_h, g);
+      block_add(t, g, g, w, B);
+      acc[l][0] += B[0][0];
+      acc[l][1] += B[1][1];
+      acc[l][2] += B[2][2];
+      acc[l][3] += B[1][2];
+      acc[l][4] += B[0][2];
+      acc[l][5] += B[0][1];
+    }
+  }
+  const int64_t np1 = n + 1;
+#pragma unroll
+  for (int l = 0; l < 8; ++l) {
+    const int64_t node = (ea + (l & 1)) + np1 * ((eb + ((l >> 1) & 1)) + np1 * (ec + (l >> 2)));
+#pragma unroll
+    for (int k = 0; k < 6; ++k) atomic_add(blk + 6 * node + k, acc[l][k]);
+  }
+}
+
+// Blocks of a CSR matrix with sorted columns: row 3a+c holds columns 3a..3a+2 next to each other.
+template <typename T>
+__global__ void csr_block_kernel(int64_t n_dof, const int32_t* rp, const int32_t* ci, const T* v, T* blk) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_dof; r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t node = r / 3;
+    const int c = (int)(r - 3 * node);
+    T row[3] = {0, 0, 0};
+    int lo = rp[r], hi = rp[r + 1] - 1;
+    while (lo <= hi) {  // first stored column >= 3 node
+      const int mid = (lo + hi) >> 1;
+      if (ci[mid] < 3 * node)
+        lo = mid + 1;
+      else
+        hi = mid - 1;
+    }
+    for (int k = lo; k < rp[r + 1] && ci[k] < 3 * node + 3; ++k) row[ci[k] - 3 * node] = v[k];
+    T* b = blk + 6 * node;
+    if (c == 0) {
+      b[0] = row[0];
+      b[5] = row[1];
+      b[4] = row[2];
+    } else if (c == 1) {
+      b[1] = row[1];
+      b[3] = row[2];
+    } else {
+      b[2] = row[2];
+    }
+  }
+}
+
+// In place: eliminate constrained components (zero row and column, 1 on the diagonal), then invert.
+// The inverse is formed in double precision from the adjugate.
+template <typename T>
+__global__ void block_inv_kernel(int64_t n_nodes, const uint8_t* mask, T* blk, int* flags) {
+  for (int64_t nd = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; nd < n_nodes;
+       nd += (int64_t)gridDim.x * blockDim.x) {
+    T* b = blk + 6 * nd;
+    double m00 = b[0], m11 = b[1], m22 = b[2], m12 = b[3], m02 = b[4], m01 = b[5];
+    if (mask) {
+      const bool c0 = mask[3 * nd], c1 = mask[3 * nd + 1], c2 = mask[3 * nd + 2];
+      if (c0) m00 = 1, m01 = 0, m02 = 0;
+      if (c1) m11 = 1, m01 = 0, m12 = 0;
+      if (c2) m22 = 1, m02 = 0, m12 = 0;
+    }
+    const double a00 = m11 * m22 - m12 * m12, a01 = m02 * m12 - m01 * m22, a02 = m01 * m12 - m02 * m11;
+    const double a11 = m00 * m22 - m02 * m02, a12 = m01 * m02 - m00 * m12, a22 = m00 * m11 - m01 * m01;
+    const double det = m00 * a00 + m01 * a01 + m02 * a02;
+    if (!(det > 0.0) && flags) atomicOr(flags, 2);
+    const double id = 1.0 / det;
+    b[0] = T(a00 * id);
+    b[1] = T(a11 * id);
+    b[2] = T(a22 * id);
+    b[3] = T(a12 * id);
+    b[4] = T(a02 * id);
+    b[5] = T(a01 * id);
+  }
+}
+
+template <typename T> static hipError_t launch_block_t(const fe_problem* p, const int32_t* rp, const int32_t* ci,
+                                                       const T* v, T* blk, hipStream_t s) {
+  if (rp) {
+    hipLaunchKernelGGL(csr_block_kernel<T>, dim3(vgrid(p->n_dof)), dim3(VBLOCK), 0, s, p->n_dof, rp, ci, v, blk);
+  } else {
+    hipLaunchKernelGGL(fill_kernel<T>, dim3(vgrid(6 * p->n_nodes)), dim3(VBLOCK), 0, s, blk, 6 * p->n_nodes, T(0));
+    const TanArgs a = tan_args(p);
+    const dim3 grid((unsigned)((p->n_el + 255) / 256));
+    switch (p->model_set) {
+      case MS_J2: hipLaunchKernelGGL((block_diag_kernel<T, MS_J2>), grid, dim3(256), 0, s, a, blk); break;
+      case MS_NH: hipLaunchKernelGGL((block_diag_kernel<T, MS_NH>), grid, dim3(256), 0, s, a, blk); break;
+      default: hipLaunchKernelGGL((block_diag_kernel<T, MS_LINEAR>), grid, dim3(256), 0, s, a, blk);
+    }
+  }
+  hipLaunchKernelGGL(block_inv_kernel<T>, dim3(vgrid(p->n_nodes)), dim3(VBLOCK), 0, s, p->n_nodes, p->mask, blk,
+                     p->flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_jacobi(const fe_problem* p, const int32_t* rp, const int32_t* ci, const void* v, void* blk,
+                               hipStream_t s) {
+  return p->prec == FE_F64 ? launch_block_t(p, rp, ci, (const double*)v, (double*)blk, s)
+                           : launch_block_t(p, rp, ci, (const float*)v, (float*)blk, s);
+}
+
+// ---------------------------------------------------------------------------
 // vector kernels
 
 template <typename T> __global__ void lift_kernel(int n, double h, const uint8_t* mask, T* u, int zero_free,
@@ -1443,19 +1581,27 @@ hipError_t launch_dot(const fe_problem* p, const void* a, const void* b, int64_t
 //   update k:         alpha = rz / p.q, x += alpha p, r -= alpha q, q = 0, partials of r.r, r.M^-1 r
 
 // x = 0, r = b, q = 0, p = 0, d <- 1/d; partials of b.b and b.M^-1 b (CG_UGRID blocks)
+// (block: M already holds the inverse blocks and is left unchanged)
 template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_init_kernel(
-    int64_t n, const T* b, T* x, T* r, T* p, T* q, T* dinv, CgCtrl* ctrl, double rtol, int max_it, double* pu) {
+    int64_t n, const T* b, T* x, T* r, T* p, T* q, T* dinv, int block, CgCtrl* ctrl, double rtol, int max_it,
+    double* pu) {
   __shared__ double sh[VBLOCK / 64];
   double rz = 0, bb = 0;
   for (int64_t i = (int64_t)blockIdx.x * VBLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * VBLOCK) {
     const T bi = b[i];
-    const T di = T(1) / dinv[i];
-    dinv[i] = di;
+    T zi;
+    if (block) {
+      zi = pc_apply(dinv, b, i, 1);
+    } else {
+      const T di = T(1) / dinv[i];
+      dinv[i] = di;
+      zi = di * bi;
+    }
     x[i] = 0;
     r[i] = bi;
     q[i] = 0;
     p[i] = 0;
-    rz += (double)bi * (double)(di * bi);
+    rz += (double)bi * (double)zi;
     bb += (double)bi * (double)bi;
   }
   rz = block_sum(rz, sh);
@@ -1476,7 +1622,7 @@ template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_init_kernel(
 
 // CSR path: direction step as a kernel of its own (the mat-vec needs the whole p first)
 template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_direction_kernel(int64_t n, const T* r,
-                                                                                     const T* dinv, T* p,
+                                                                                     const T* dinv, int block, T* p,
                                                                                      CgCtrl* ctrl, const double* pu,
                                                                                      long k) {
   __shared__ double sh[VBLOCK / 64], bc[2];
@@ -1485,14 +1631,15 @@ template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_direction_ker
   if (!cg_direction_step(ctrl, pu, k, sh, bc, beta)) return;
   const T tb = T(beta);
   for (int64_t i = (int64_t)blockIdx.x * VBLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * VBLOCK)
-    p[i] = dinv[i] * r[i] + tb * p[i];
+    p[i] = pc_apply(dinv, r, i, block) + tb * p[i];
 }
 
-// alpha = rz / p.q (from the operator's partials); x += alpha p; r -= alpha q; q = 0
+// alpha = rz / p.q (from the operator's partials); x += alpha p; r -= alpha q; q = 0.
+// One thread per node, so r.M^-1 r uses the node's three new residual entries.
 template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_update_kernel(int64_t n, T* x, T* r, const T* p,
-                                                                                  T* q, const T* dinv, CgCtrl* ctrl,
-                                                                                  const double* pa, int nba,
-                                                                                  double* pu, long k) {
+                                                                                  T* q, const T* dinv, int block,
+                                                                                  CgCtrl* ctrl, const double* pa,
+                                                                                  int nba, double* pu, long k) {
   __shared__ double sh[VBLOCK / 64], bc[1];
   if (ctrl->status) return;
   const double pq = sum_partials_all(pa, nba, sh, bc);
@@ -1507,13 +1654,28 @@ template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_update_kernel
   if (st != CG_RUNNING) return;
   const T ta = T(alpha);
   double rr = 0, rzn = 0;
-  for (int64_t i = (int64_t)blockIdx.x * VBLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * VBLOCK) {
-    x[i] += ta * p[i];
-    const T ri = r[i] - ta * q[i];
-    r[i] = ri;
-    q[i] = 0;
-    rr += (double)ri * (double)ri;
-    rzn += (double)ri * (double)(dinv[i] * ri);
+  const int64_t n_nodes = n / 3;
+  for (int64_t nd = (int64_t)blockIdx.x * VBLOCK + threadIdx.x; nd < n_nodes; nd += (int64_t)gridDim.x * VBLOCK) {
+    T rn[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t i = 3 * nd + c;
+      x[i] += ta * p[i];
+      rn[c] = r[i] - ta * q[i];
+      r[i] = rn[c];
+      q[i] = 0;
+      rr += (double)rn[c] * (double)rn[c];
+    }
+    if (block) {
+      const T* m = dinv + 6 * nd;
+      const T z0 = m[0] * rn[0] + m[5] * rn[1] + m[4] * rn[2];
+      const T z1 = m[5] * rn[0] + m[1] * rn[1] + m[3] * rn[2];
+      const T z2 = m[4] * rn[0] + m[3] * rn[1] + m[2] * rn[2];
+      rzn += (double)rn[0] * (double)z0 + (double)rn[1] * (double)z1 + (double)rn[2] * (double)z2;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rzn += (double)rn[c] * (double)(dinv[3 * nd + c] * rn[c]);
+    }
   }
   rr = block_sum(rr, sh);
   rzn = block_sum(rzn, sh);
@@ -1527,7 +1689,7 @@ template <typename T>
 static hipError_t cg_init_t(const fe_problem* p, const T* b, T* x, double rtol, int max_it, hipStream_t s) {
   const int64_t n = p->n_dof;
   hipLaunchKernelGGL(cg_init_kernel<T>, dim3(CG_UGRID), dim3(VBLOCK), 0, s, n, b, x, (T*)p->w_r, (T*)p->w_p,
-                     (T*)p->w_q, (T*)p->w_d, p->ctrl, rtol, max_it, p->partials + cg_pa_size(p));
+                     (T*)p->w_q, (T*)pc_buffer(p), p->precond, p->ctrl, rtol, max_it, p->partials + cg_pa_size(p));
   return hipGetLastError();
 }
 
@@ -1608,7 +1770,8 @@ static hipError_t cg_operator_t(const fe_problem* p, int op, const int32_t* rp, 
   a.sur_map = p->sur_map;
   a.sur_D = p->sur_D;
   a.cg_r = p->w_r;
-  a.cg_dinv = p->w_d;
+  a.cg_dinv = pc_buffer(p);
+  a.cg_block = p->precond;
   a.cg_pnew = cg_p_new(p, op, k);
   a.cg_pold = (a.cg_pnew == p->w_p) ? p->w_p2 : p->w_p;
   a.ctrl = p->ctrl;
@@ -1628,7 +1791,8 @@ hipError_t cg_operator(const fe_problem* p, int op, const int32_t* rp, const int
 template <typename T> static hipError_t cg_pre_t(const fe_problem* p, int op, long k, hipStream_t s) {
   if (op != FE_OP_CSR) return hipSuccess;
   hipLaunchKernelGGL(cg_direction_kernel<T>, dim3(CG_UGRID), dim3(VBLOCK), 0, s, p->n_dof, (const T*)p->w_r,
-                     (const T*)p->w_d, (T*)p->w_p, p->ctrl, (const double*)(p->partials + cg_pa_size(p)), k);
+                     (const T*)pc_buffer(p), p->precond, (T*)p->w_p, p->ctrl,
+                     (const double*)(p->partials + cg_pa_size(p)), k);
   return hipGetLastError();
 }
 
@@ -1640,8 +1804,8 @@ template <typename T> static hipError_t cg_vectors_t(const fe_problem* p, int op
   const int64_t n = p->n_dof;
   T* P = (T*)cg_p_new(p, op, k);
   hipLaunchKernelGGL(cg_update_kernel<T>, dim3(CG_UGRID), dim3(VBLOCK), 0, s, n, x, (T*)p->w_r, (const T*)P,
-                     (T*)p->w_q, (const T*)p->w_d, p->ctrl, (const double*)p->partials, cg_operator_grid(p, op),
-                     p->partials + cg_pa_size(p), k);
+                     (T*)p->w_q, (const T*)pc_buffer(p), p->precond, p->ctrl, (const double*)p->partials,
+                     cg_operator_grid(p, op), p->partials + cg_pa_size(p), k);
   return hipGetLastError();
 }
 

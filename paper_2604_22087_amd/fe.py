@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libfe.so")
 F64, F32 = 0, 1
 LINEAR, J2, NEOHOOKE = 0, 1, 2
 OP_CSR, OP_MATFREE = 0, 1
+PC_JACOBI, PC_BLOCK_JACOBI = 0, 1
 APPLY_BC, STORE_TANGENT = 1, 2
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "HIP runtime error", 3: "out of device memory",
@@ -58,6 +59,7 @@ SIGNATURES = [
     ("fe_apply_matfree", _i32, [_vp, _vp, _vp, _i32, _vp]),
     ("fe_apply_csr", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("fe_diagonal", _i32, [_vp, _vp, _i32, _vp]),
+    ("fe_set_preconditioner", _i32, [_vp, _i32]),
     ("fe_pcg", _i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _dbl, _i32, ctypes.POINTER(PcgInfo), _vp]),
     ("fe_vjp", _i32, [_vp, _vp, _vp, _vp, _vp]),
     ("fe_newton", _i32, [_vp, ctypes.POINTER(_dbl), _i32, ctypes.POINTER(NewtonOpts), _vp, _vp,
@@ -237,6 +239,10 @@ class Problem:
         d = self.vector() if d is None else self._real(d, self.n_dof, "d")
         _check(self.lib.fe_diagonal(self.handle, _ptr(d), int(apply_bc), _stream()), "fe_diagonal")
         return d
+
+    def set_preconditioner(self, kind):
+        """PC_JACOBI (point) or PC_BLOCK_JACOBI (3x3 node blocks) for pcg and newton."""
+        _check(self.lib.fe_set_preconditioner(self.handle, int(kind)), "fe_set_preconditioner")
 
     def pcg(self, b, x=None, op=OP_MATFREE, csr=None, rtol=1e-10, max_it=100000, check=True):
         self._real(b, self.n_dof, "b")
