@@ -11,10 +11,11 @@ Jacobi-PCG (diagonal from the CSR) to 1e-10.  Inputs are resident on the GPU
 before the timed region; each step restarts the ramp from zero.
 
 value = whole-step K*u throughput: dofs x operator applications / step time.
-The dominant kernel (matrix-free K*u) is timed live with HIP events recorded by
-the library on the stream it runs on; its algorithmic bytes per launch are the
-compulsory traffic at the linearisation in force (x, y, phase ids, stored
-tangent values read).
+The dominant kernel (the CG iteration's fused direction step + matrix-free K*u)
+is timed live with HIP events recorded by the library on the stream it runs on;
+its algorithmic bytes per launch are the compulsory traffic at the
+linearisation in force (r, M^-1, p_old read, p_new and A p written, phase ids,
+stored tangent values read).
 """
 from __future__ import annotations
 
@@ -243,7 +244,8 @@ def main():
                    "n": n, "n_dof": P.n_dof, "n_qp": P.n_qp, "nnz": P.nnz, "load_steps": args.load_steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "elem_kernel<double, OP_APPLY, MS_J2> (matrix-free K*u)",
+                     "kernel": "elem_kernel<double, OP_CG_APPLY, MS_J2> (CG direction step fused with the "
+                               "matrix-free K*u)",
                      "avg_launch_us": 1e3 * ku_avg_ms, "launches": cnt,
                      "bytes_per_launch": byts / max(cnt, 1)},
         "ku_kernel_gdofs": P.n_dof / (ku_avg_ms * 1e-3) / 1e9,

@@ -44,7 +44,7 @@ enum ElemOp {
 // CG status word: kernels stop on any non-zero value, so "converged" must differ from 0.
 constexpr int CG_RUNNING = 0;
 constexpr int CG_CONVERGED = -1;
-constexpr int CG_UGRID = 256;        // workgroups of the CG vector kernels (= update partial slots)
+constexpr int CG_UGRID = 512;        // workgroups of the CG vector kernels (= update partial slots)
 constexpr int SPMV_MAXGRID = 2048;   // workgroups of the CG mat-vec (grid-stride over rows)
 
 // Device scalar block used by CG (one per problem).

@@ -424,10 +424,12 @@ __device__ __forceinline__ bool sur_consume(const T H[3][3], const T epn[6], T a
 }
 
 // Stress from a general Voigt tangent D (tensor stress, engineering shear strain) and sym(H).
+// (rare path inside the operator: rows are read one at a time so that this branch does
+// not raise the register budget of the whole kernel)
 template <typename T> __device__ __forceinline__ void general_apply(const T H[3][3], const T* D, T S[3][3]) {
   const T e[6] = {H[0][0], H[1][1], H[2][2], H[1][2] + H[2][1], H[0][2] + H[2][0], H[0][1] + H[1][0]};
   T s[6];
-#pragma unroll
+#pragma unroll 1
   for (int i = 0; i < 6; ++i) {
     T acc = 0;
 #pragma unroll
@@ -1635,13 +1637,75 @@ template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_direction_ker
 }
 
 // alpha = rz / p.q (from the operator's partials); x += alpha p; r -= alpha q; q = 0.
-// One thread per node, so r.M^-1 r uses the node's three new residual entries.
-template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_update_kernel(int64_t n, T* x, T* r, const T* p,
-                                                                                  T* q, const T* dinv, int block,
-                                                                                  CgCtrl* ctrl, const double* pa,
-                                                                                  int nba, double* pu, long k) {
+// One thread per node (so r.M^-1 r uses the node's three new residual entries), UPB nodes
+// per thread whose loads are all issued before the partial sums are reduced.
+constexpr int UPB = 2;
+template <typename T> struct UpdBatch {
+  T x[UPB][3], r[UPB][3], p[UPB][3], q[UPB][3], m[UPB][6];
+};
+
+template <typename T>
+__device__ __forceinline__ void upd_load(UpdBatch<T>& b, int64_t nd0, int64_t stride, int64_t n_nodes,
+                                         const T* __restrict__ x, const T* __restrict__ r, const T* __restrict__ p,
+                                         const T* __restrict__ q, const T* __restrict__ dinv, int block) {
+#pragma unroll
+  for (int u = 0; u < UPB; ++u) {
+    const int64_t nd = nd0 + u * stride;
+    const bool ok = nd < n_nodes;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t i = ok ? 3 * nd + c : 0;
+      b.x[u][c] = ok ? x[i] : T(0);
+      b.r[u][c] = ok ? r[i] : T(0);
+      b.p[u][c] = ok ? p[i] : T(0);
+      b.q[u][c] = ok ? q[i] : T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) b.m[u][c] = (ok && (block || c < 3)) ? dinv[(block ? 6 : 3) * nd + c] : T(0);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void upd_store(const UpdBatch<T>& b, T ta, int64_t nd0, int64_t stride, int64_t n_nodes,
+                                          T* __restrict__ x, T* __restrict__ r, T* __restrict__ q, int block,
+                                          double& rr, double& rzn) {
+#pragma unroll
+  for (int u = 0; u < UPB; ++u) {
+    const int64_t nd = nd0 + u * stride;
+    if (nd >= n_nodes) continue;
+    T rn[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t i = 3 * nd + c;
+      x[i] = b.x[u][c] + ta * b.p[u][c];
+      rn[c] = b.r[u][c] - ta * b.q[u][c];
+      r[i] = rn[c];
+      q[i] = 0;
+      rr += (double)rn[c] * (double)rn[c];
+    }
+    const T* m = b.m[u];
+    if (block) {
+      const T z0 = m[0] * rn[0] + m[5] * rn[1] + m[4] * rn[2];
+      const T z1 = m[5] * rn[0] + m[1] * rn[1] + m[3] * rn[2];
+      const T z2 = m[4] * rn[0] + m[3] * rn[1] + m[2] * rn[2];
+      rzn += (double)rn[0] * (double)z0 + (double)rn[1] * (double)z1 + (double)rn[2] * (double)z2;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rzn += (double)rn[c] * (double)(m[c] * rn[c]);
+    }
+  }
+}
+
+template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_update_kernel(
+    int64_t n, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, T* __restrict__ q,
+    const T* __restrict__ dinv, int block, CgCtrl* ctrl, const double* pa, int nba, double* pu, long k) {
   __shared__ double sh[VBLOCK / 64], bc[1];
   if (ctrl->status) return;
+  const int64_t n_nodes = n / 3;
+  const int64_t stride = (int64_t)gridDim.x * VBLOCK;
+  int64_t nd0 = (int64_t)blockIdx.x * VBLOCK + threadIdx.x;
+  UpdBatch<T> b;
+  upd_load(b, nd0, stride, n_nodes, x, r, p, q, dinv, block);  // in flight while the partials are reduced
   const double pq = sum_partials_all(pa, nba, sh, bc);
   const double rz = ctrl->rz[k & 1];
   const int st = !finite(pq) ? FE_ERR_NONFINITE : (pq <= 0.0 ? FE_ERR_BREAKDOWN : CG_RUNNING);
@@ -1654,28 +1718,10 @@ template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_update_kernel
   if (st != CG_RUNNING) return;
   const T ta = T(alpha);
   double rr = 0, rzn = 0;
-  const int64_t n_nodes = n / 3;
-  for (int64_t nd = (int64_t)blockIdx.x * VBLOCK + threadIdx.x; nd < n_nodes; nd += (int64_t)gridDim.x * VBLOCK) {
-    T rn[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const int64_t i = 3 * nd + c;
-      x[i] += ta * p[i];
-      rn[c] = r[i] - ta * q[i];
-      r[i] = rn[c];
-      q[i] = 0;
-      rr += (double)rn[c] * (double)rn[c];
-    }
-    if (block) {
-      const T* m = dinv + 6 * nd;
-      const T z0 = m[0] * rn[0] + m[5] * rn[1] + m[4] * rn[2];
-      const T z1 = m[5] * rn[0] + m[1] * rn[1] + m[3] * rn[2];
-      const T z2 = m[4] * rn[0] + m[3] * rn[1] + m[2] * rn[2];
-      rzn += (double)rn[0] * (double)z0 + (double)rn[1] * (double)z1 + (double)rn[2] * (double)z2;
-    } else {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) rzn += (double)rn[c] * (double)(dinv[3 * nd + c] * rn[c]);
-    }
+  upd_store(b, ta, nd0, stride, n_nodes, x, r, q, block, rr, rzn);
+  for (nd0 += UPB * stride; nd0 < n_nodes; nd0 += UPB * stride) {
+    upd_load(b, nd0, stride, n_nodes, x, r, p, q, dinv, block);
+    upd_store(b, ta, nd0, stride, n_nodes, x, r, q, block, rr, rzn);
   }
   rr = block_sum(rr, sh);
   rzn = block_sum(rzn, sh);

@@ -67,20 +67,34 @@ def test_adjoint_fullsize_fd_and_euler():
     un = u.double().cpu().numpy()
     assert rel_err(g[picks], oadj.vjp_scale(sub, un, un)) <= 1e-12
 
-    def energy(Evec):
+    def energy(Evec, rtol=1e-13):
         P.set_materials(phase, [fe.LINEAR], [(1.0, 0.3)], torch.tensor(Evec, device="cuda"))
-        uu = P.newton([EB], op=fe.OP_MATFREE, pcg_rtol=1e-13, newton_rtol=1e-12)[0]
+        uu = P.newton([EB], op=fe.OP_MATFREE, pcg_rtol=rtol, newton_rtol=1e-12)[0]
         e_el = (torch.tensor(Evec, device="cuda") * P.vjp(uu, uu)).double().cpu().numpy()
         return math.fsum(e_el.tolist())
 
-    h = 1e-6
-    errs = []
-    for k in picks:
-        Ep, Em = E.copy(), E.copy()
-        Ep[k] += h
-        Em[k] -= h
-        fd = (energy(Ep) - energy(Em)) / (2 * h)
-        errs.append(abs(fd - g[k]) / abs(g[k]))
-    errs = np.array(errs)
-    print(f"  FD vs adjoint on 64 elements: median {np.median(errs):.2e} max {errs.max():.2e}", flush=True)
-    assert errs.max() <= 1e-4
+    # Noise floor of one energy evaluation: the same E solved along two CG paths.  A
+    # central difference with step h carries about 2 eps_J / (2 h) of that noise; at
+    # h = 1e-6 the difference J(E+h) - J(E-h) is ~1e-12 of J, near FP64 resolution.
+    eps_j = max(abs(energy(E, 1e-13) - energy(E, 1e-12)), abs(float(J)) * 2.0 ** -52)
+
+    def fd_errors(h, picks_h):
+        errs, bounds = [], []
+        for k in picks_h:
+            Ep, Em = E.copy(), E.copy()
+            Ep[k] += h
+            Em[k] -= h
+            fd = (energy(Ep) - energy(Em)) / (2 * h)
+            errs.append(abs(fd - g[k]) / abs(g[k]))
+            bounds.append(2 * eps_j / (2 * h) / abs(g[k]))
+        return np.array(errs), np.array(bounds)
+
+    errs, noise = fd_errors(1e-6, picks)
+    print(f"  FD (h=1e-6) vs adjoint on 64 elements: median {np.median(errs):.2e} max {errs.max():.2e}; "
+          f"noise bound median {np.median(noise):.2e} (eps_J {eps_j:.2e})", flush=True)
+    assert np.median(errs) <= 1e-4
+    assert np.all(errs <= 1e-5 + 4 * noise)
+    # a larger step on 16 of the picks: noise 100x lower, truncation ~(h/E)^2
+    errs4, noise4 = fd_errors(1e-4, picks[:16])
+    print(f"  FD (h=1e-4) on 16 elements: max {errs4.max():.2e}", flush=True)
+    assert np.all(errs4 <= 1e-6 + 4 * noise4)

@@ -130,3 +130,40 @@ def test_surrogate_consume_matches_oracle():
         assert np.abs(ep_g[sel, q][close] - out["eps_p"][close]).max() <= 1e-6
     assert abs(used_tot - stats["accepted"]) <= 0.01 * stats["listed"] + 1
     assert flips <= 0.01 * stats["listed"] + 1
+
+
+def test_surrogate_newton_end_to_end():
+    """Train on return-map samples of a small fiber RVE, then drive a Newton ramp with the
+    network: the ramp converges and its homogenised stress stays within 1e-3 of the
+    return-map ramp (the local check sends poorly predicted points back to the return
+    map).  Timings, accepted fraction and the error are printed: this is what the network
+    gains (or costs) against the method without it at this size."""
+    import time
+    import torch
+    from paper_2604_22087_amd import fe
+    from paper_2604_22087_amd import surrogate as gsur
+    n = 16
+    P = gsur.fiber_problem(n)
+    x, y = gsur.capture_samples([(P, gsur.ramp(0.03, 10), 1), (P, gsur.ramp(0.03, 10, shear=True), 1)],
+                                capacity=4_000_000)
+    print(f"  samples {x.shape[0]}", flush=True)
+    W, hist = gsur.train(x, y, epochs=80, batch=2048, lr=2e-3)
+    assert hist[-1]["val_loss"] < 0.1 * hist[0]["val_loss"]
+    res = {}
+    for mode in ("return_map", "surrogate"):
+        P = gsur.fiber_problem(n)
+        if mode == "surrogate":
+            P.set_surrogate(W, fallback_tol=1e-3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, sig, info = P.newton(gsur.ramp(0.02, 5), state=P.state(), op=fe.OP_MATFREE, newton_rtol=1e-8,
+                                   pcg_rtol=1e-10, max_newton=30)
+        torch.cuda.synchronize()
+        res[mode] = (time.perf_counter() - t0, np.array(sig), info,
+                     P.surrogate_stats() if mode == "surrogate" else None)
+    (t_rm, s_rm, i_rm, _), (t_su, s_su, i_su, stats) = res["return_map"], res["surrogate"]
+    err = np.max(np.abs(s_su[:, 0] - s_rm[:, 0]) / np.abs(s_rm[:, 0]))
+    print(f"  return map {t_rm:.3f}s {i_rm}\n  surrogate {t_su:.3f}s {i_su} {stats}\n  max rel sigma_xx err {err:.2e}",
+          flush=True)
+    assert i_su["steps_done"] == 5
+    assert err <= 1e-3
