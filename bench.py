@@ -151,6 +151,49 @@ def neohooke_leg(n):
     return res
 
 
+def surrogate_leg(n):
+    """Learned-surrogate leg: n^3 sphere RVE (r = 0.3 linear inclusion E = 70, nu = 0.22, J2 matrix of the
+    fiber workload), eps_xx ramp to 0.02 in 10 steps, matrix-free Jacobi-PCG, Newton 1e-6 / PCG 1e-8 for
+    both constitutive paths; the surrogate runs at plastic-trial points with a 1e-3 local check and
+    return-map fallback.  Reports wall times, solver work and the homogenised-stress error."""
+    import torch
+    from paper_2604_22087_amd import fe
+    from paper_2604_22087_amd import surrogate as S
+    W = S.load_weights()
+    if W is None:
+        return {"skipped": "no trained parameters (python -m paper_2604_22087_amd.surrogate writes them)"}
+    out = {}
+    for mode in ("return_map", "surrogate"):
+        P = S.sphere_problem(n)
+        if mode == "surrogate":
+            P.set_surrogate(W, fallback_tol=1e-3)
+        u, st = P.vector(), P.state()
+        torch.cuda.synchronize()
+        P.profile(True)
+        t0 = time.perf_counter()
+        _, _, sig, info = P.newton(S.ramp(0.02, 10), u=u, state=st, op=fe.OP_MATFREE, newton_rtol=1e-6,
+                                   pcg_rtol=1e-8, max_newton=30, check=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        pr = P.profile_read()
+        P.profile(False)
+        rc, rms, _ = pr["residual"]
+        kc, kms, _ = pr["matfree_apply"]
+        out[mode] = {"seconds": dt, "status": info["status"], "newton_iterations": info["newton_iterations"],
+                     "pcg_iterations": info["pcg_iterations"], "residual_avg_us": 1e3 * rms / max(rc, 1),
+                     "ku_avg_us": 1e3 * kms / max(kc, 1), "sigma_bar_xx": [s_[0] for s_ in sig]}
+        if mode == "surrogate":
+            out[mode]["points"] = P.surrogate_stats()
+        del P
+    s_rm = np.array(out["return_map"]["sigma_bar_xx"])
+    s_su = np.array(out["surrogate"]["sigma_bar_xx"])
+    out["max_rel_sigma_bar_err"] = float(np.max(np.abs(s_su - s_rm) / np.abs(s_rm)))
+    out["time_ratio_surrogate_over_return_map"] = out["surrogate"]["seconds"] / out["return_map"]["seconds"]
+    out["workload"] = (f"{n}^3 sphere RVE, J2 matrix, eps_xx -> 0.02 in 10 steps, Newton 1e-6, PCG 1e-8; "
+                       f"MLP 13-128-128-128-6 with 1e-3 local check and return-map fallback")
+    return out
+
+
 def cpu_baseline(n, phase, gpu_info, path):
     """The FP64 oracle on a bounded sample of the same workload (host cores)."""
     from oracle import solver
@@ -190,6 +233,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 ramp")
     ap.add_argument("--nh", type=int, default=0, help="also run the finite-strain Neo-Hookean leg at this n (0: skip)")
+    ap.add_argument("--surrogate", type=int, default=96, help="n of the surrogate-vs-return-map leg (0: skip)")
     ap.add_argument("--copy-calib", action="store_true", help="run only a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -274,6 +318,9 @@ def main():
                        "pcg_iterations": info32["pcg_iterations"],
                        "operators": operator_rates(P32, u32, s32)}
         del P32
+    if args.surrogate:
+        print(f"[bench] surrogate leg {args.surrogate}^3", file=sys.stderr, flush=True)
+        out["surrogate"] = surrogate_leg(args.surrogate)
     if args.nh:
         print(f"[bench] neo-hookean leg {args.nh}^3", file=sys.stderr, flush=True)
         out["neohooke"] = neohooke_leg(args.nh)
