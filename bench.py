@@ -37,6 +37,22 @@ FIBER = (230.0, 0.2)
 MATRIX = (3.5, 0.35, 0.05, 0.1)
 
 
+def measured_traffic():
+    """HBM bytes per launch of the fused CG operator from the committed rocprofv3 counter runs
+    (FETCH_SIZE / WRITE_SIZE, scaled by a 1 GiB copy), or None when the kernel source has
+    changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "cg_operator_fiber64_f64_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2604_22087_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("fe_kernels.hip", "fe_internal.hpp"):
+        h.update(open(os.path.join(src, f), "rb").read())
+    return rec if h.hexdigest() == rec["source_sha256"] else None
+
+
 def load_path(steps=10, d=0.002):
     return [np.diag([d * k, 0.0, 0.0]) for k in range(1, steps + 1)]
 
@@ -275,6 +291,7 @@ def main():
     cnt, ms, byts = prof["matfree_apply"]
     ku_avg_ms = ms / max(cnt, 1)
     achieved = byts / max(cnt, 1) / (ku_avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic() if n == 64 else None
     rcnt, rms, _ = prof["residual"]
     tcnt, tms, _ = prof["tangent_csr"]
     out = {
@@ -287,7 +304,12 @@ def main():
                                f"Jacobi-PCG 1e-10",
                    "n": n, "n_dof": P.n_dof, "n_qp": P.n_qp, "nnz": P.nnz, "load_steps": args.load_steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic["traffic_bytes_per_launch"] if traffic else None,
+                     "traffic_note": (f"rocprofv3 FETCH_SIZE x {traffic['fetch_scale']:.3f} + WRITE_SIZE x "
+                                      f"{traffic['write_scale']:.3f} (1 GiB copy calibration), mean per launch over "
+                                      f"{traffic['workload']}, where the algorithmic bytes are "
+                                      f"{traffic['algorithmic_bytes_per_launch']:.4g}") if traffic else None,
                      "kernel": "elem_kernel<double, OP_CG_APPLY, MS_J2> (CG direction step fused with the "
                                "matrix-free K*u)",
                      "avg_launch_us": 1e3 * ku_avg_ms, "launches": cnt,

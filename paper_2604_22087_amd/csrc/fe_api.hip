@@ -58,8 +58,9 @@ static void free_dev(void* p) {
   if (p) (void)hipFree(p);
 }
 
-// Kernel timing: an event pair on the launch stream around one launch.
+// Kernel timing: an event pair recorded by the timed launch itself (see timed_launch).
 static int prof_begin(fe_problem* p, hipStream_t s, long* idx) {
+  (void)s;
   *idx = -1;
   if (!p->prof) return FE_OK;
   while (p->ev_used + 2 > p->ev_pool.size()) {
@@ -68,26 +69,37 @@ static int prof_begin(fe_problem* p, hipStream_t s, long* idx) {
     p->ev_pool.push_back(e);
   }
   *idx = (long)p->ev_used;
-  p->ev_used += 2;
-  HIPCHK(hipEventRecord(p->ev_pool[*idx], s));
+  LaunchEvents& ev = launch_events();
+  ev.start = p->ev_pool[*idx];
+  ev.stop = p->ev_pool[*idx + 1];
+  ev.armed = true;
+  ev.used = false;
   return FE_OK;
 }
 
 static int prof_end(fe_problem* p, hipStream_t s, long idx, int cls) {
+  (void)s;
   if (idx < 0) return FE_OK;
-  HIPCHK(hipEventRecord(p->ev_pool[idx + 1], s));
+  LaunchEvents& ev = launch_events();
+  const bool used = ev.used;
+  ev.armed = false;
+  ev.used = false;
+  if (!used) return FE_OK;  // nothing was launched (the pair stays free)
+  p->ev_used += 2;
   p->prof_recs.push_back({cls, (size_t)idx});
   return FE_OK;
 }
 
 static int operator_bytes(fe_problem* p, int op, hipStream_t s, double* bytes);
 
-#define PROF(p, s, cls, launch_expr)          \
-  do {                                        \
-    long _pi;                                 \
-    if (int _st = prof_begin(p, s, &_pi)) return _st; \
-    HIPCHK(launch_expr);                      \
-    if (int _st = prof_end(p, s, _pi, cls)) return _st; \
+#define PROF(p, s, cls, launch_expr)                    \
+  do {                                                  \
+    long _pi;                                           \
+    if (int _st = prof_begin(p, s, &_pi)) return _st;   \
+    const hipError_t _le = (launch_expr);               \
+    const int _pe = prof_end(p, s, _pi, cls);           \
+    HIPCHK(_le);                                        \
+    if (_pe) return _pe;                                \
   } while (0)
 
 extern "C" {

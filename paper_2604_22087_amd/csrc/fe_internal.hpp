@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -175,6 +176,26 @@ namespace fe {
 size_t real_size(const fe_problem* p);
 void set_error(const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
+
+// Kernel timing: when armed, the next timed launch records `start` and `stop` inside its own
+// dispatch (hipExtLaunchKernelGGL), so the interval is the kernel alone, without separate
+// marker packets on the stream.  One per host thread.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool armed = false, used = false;
+};
+LaunchEvents& launch_events();
+
+template <typename F, typename... Args>
+inline void timed_launch(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, Args... args) {
+  LaunchEvents& ev = launch_events();
+  if (ev.armed && !ev.used) {
+    ev.used = true;
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, ev.start, ev.stop, 0u, args...);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+  }
+}
 
 // kernel launchers (fe_kernels.hip); each returns hipError_t of the launch
 hipError_t launch_elem(const fe_problem* p, int op, const ElemArgs& a, hipStream_t s);

@@ -20,6 +20,11 @@
 
 namespace fe {
 
+LaunchEvents& launch_events() {
+  static thread_local LaunchEvents ev;
+  return ev;
+}
+
 constexpr int TX = 16, TY = 4, TZ = 4;
 constexpr int NX = TX + 1, NY = TY + 1, NZ = TZ + 1, NN = NX * NY * NZ;
 constexpr int EBLOCK = TX * TY * TZ;
@@ -915,13 +920,13 @@ static hipError_t launch_elem_t(const fe_problem* p, const ElemArgs& a, const in
   const dim3 grid(elem_grid(p->n)), block(EBLOCK);
   switch (p->model_set) {
     case MS_J2:
-      hipLaunchKernelGGL((elem_kernel<T, OP, MS_J2>), grid, block, 0, s, a, stop);
+      timed_launch((elem_kernel<T, OP, MS_J2>), grid, block, 0, s, a, stop);
       break;
     case MS_NH:
-      hipLaunchKernelGGL((elem_kernel<T, OP, MS_NH>), grid, block, 0, s, a, stop);
+      timed_launch((elem_kernel<T, OP, MS_NH>), grid, block, 0, s, a, stop);
       break;
     default:
-      hipLaunchKernelGGL((elem_kernel<T, OP, MS_LINEAR>), grid, block, 0, s, a, stop);
+      timed_launch((elem_kernel<T, OP, MS_LINEAR>), grid, block, 0, s, a, stop);
   }
   return hipGetLastError();
 }
@@ -1263,16 +1268,16 @@ hipError_t launch_tangent_csr(const fe_problem* p, void* vals, int apply_bc, hip
   if (p->prec == FE_F64) {
     double* v = (double*)vals;
     switch (p->model_set) {
-      case MS_J2: hipLaunchKernelGGL((tangent_csr_kernel<double, MS_J2>), grid, dim3(256), 0, s, a, v, apply_bc); break;
-      case MS_NH: hipLaunchKernelGGL((tangent_csr_kernel<double, MS_NH>), grid, dim3(256), 0, s, a, v, apply_bc); break;
-      default: hipLaunchKernelGGL((tangent_csr_kernel<double, MS_LINEAR>), grid, dim3(256), 0, s, a, v, apply_bc);
+      case MS_J2: timed_launch((tangent_csr_kernel<double, MS_J2>), grid, dim3(256), 0, s, a, v, apply_bc); break;
+      case MS_NH: timed_launch((tangent_csr_kernel<double, MS_NH>), grid, dim3(256), 0, s, a, v, apply_bc); break;
+      default: timed_launch((tangent_csr_kernel<double, MS_LINEAR>), grid, dim3(256), 0, s, a, v, apply_bc);
     }
   } else {
     float* v = (float*)vals;
     switch (p->model_set) {
-      case MS_J2: hipLaunchKernelGGL((tangent_csr_kernel<float, MS_J2>), grid, dim3(256), 0, s, a, v, apply_bc); break;
-      case MS_NH: hipLaunchKernelGGL((tangent_csr_kernel<float, MS_NH>), grid, dim3(256), 0, s, a, v, apply_bc); break;
-      default: hipLaunchKernelGGL((tangent_csr_kernel<float, MS_LINEAR>), grid, dim3(256), 0, s, a, v, apply_bc);
+      case MS_J2: timed_launch((tangent_csr_kernel<float, MS_J2>), grid, dim3(256), 0, s, a, v, apply_bc); break;
+      case MS_NH: timed_launch((tangent_csr_kernel<float, MS_NH>), grid, dim3(256), 0, s, a, v, apply_bc); break;
+      default: timed_launch((tangent_csr_kernel<float, MS_LINEAR>), grid, dim3(256), 0, s, a, v, apply_bc);
     }
   }
   return hipGetLastError();
@@ -1305,7 +1310,7 @@ template <typename T>
 static hipError_t launch_spmv_t(const fe_problem* p, const int32_t* rp, const int32_t* ci, const T* v, const T* x,
                                 T* y, const int* stop, hipStream_t s) {
   const int64_t threads = p->n_dof * SPMV_LPR;
-  hipLaunchKernelGGL((spmv_kernel<T, SPMV_LPR>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, p->n_dof,
+  timed_launch((spmv_kernel<T, SPMV_LPR>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, p->n_dof,
                      rp, ci, v, x, y, stop);
   return hipGetLastError();
 }
@@ -1797,7 +1802,7 @@ static hipError_t cg_operator_t(const fe_problem* p, int op, const int32_t* rp, 
   T* Q = (T*)p->w_q;
   double* pa = p->partials;
   if (op == FE_OP_CSR) {
-    hipLaunchKernelGGL((cg_spmv_kernel<T, SPMV_LPR>), dim3(cg_spmv_grid(p)), dim3(256), 0, s, p->n_dof, rp, ci, vals,
+    timed_launch((cg_spmv_kernel<T, SPMV_LPR>), dim3(cg_spmv_grid(p)), dim3(256), 0, s, p->n_dof, rp, ci, vals,
                        (const T*)p->w_p, Q, stop, pa);
     return hipGetLastError();
   }
