@@ -525,8 +525,11 @@ __device__ __forceinline__ void nh_apply(const T dH[3][3], const T FiT[3][3], T 
 // ---------------------------------------------------------------------------
 // element brick kernel
 
+// (at least two waves per SIMD: some FP64 instances sit at the 256-register edge, where
+// the allocator would otherwise fall back to one wave per SIMD)
 template <typename T, int OP, int MS>
-__global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* stop) {
+__global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) void elem_kernel(ElemArgs a,
+                                                                                              const int* stop) {
   constexpr bool APPLY_LIKE = (OP == OP_APPLY) || (OP == OP_CG_APPLY);
   constexpr bool NEED_L = (OP == OP_VJP) || (APPLY_LIKE && MS == MS_NH);
   __shared__ T s_x[NN * 3];
@@ -645,6 +648,20 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
 #pragma unroll
         for (int c = 0; c < 3; ++c) Px[x][y][c] = Py[x][y][c] = Pz[x][y][c] = 0;
 
+    // J2 operator: the first stored-tangent word of every Gauss point is requested up front,
+    // the five plastic-point words of the next point while the current one is computed
+    const T* tang_c = static_cast<const T*>(a.tangent);
+    T tq0[8];
+    if (APPLY_LIKE && MS == MS_J2) {
+#pragma unroll
+      for (int qq = 0; qq < 8; ++qq) tq0[qq] = pc.model == FE_J2 ? tang_c[(int64_t)qq * ne + e] : T(-1);
+    }
+    T pw[2][5];
+    auto load_pw = [&](int qp, T* w) {
+#pragma unroll
+      for (int k = 1; k < 6; ++k) w[k - 1] = tq0[qp] >= 0 ? tang_c[(int64_t)(k * 8 + qp) * ne + e] : T(0);
+    };
+    if (APPLY_LIKE && MS == MS_J2) load_pw(0, pw[0]);
     const T* st_in = static_cast<const T*>(a.state_in);
     T* st_out = static_cast<T*>(a.state_out);
     T* tang = static_cast<T*>(a.tangent);
@@ -656,6 +673,7 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
           const int qp = p + 2 * q + 4 * r;
+          if (APPLY_LIKE && MS == MS_J2 && qp < 7) load_pw(qp + 1, pw[(qp + 1) & 1]);
           T H[3][3], S[3][3];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
@@ -730,18 +748,13 @@ __global__ __launch_bounds__(EBLOCK) void elem_kernel(ElemArgs a, const int* sto
               done = true;
             } else if (APPLY_LIKE) {
               T tn[6], lp, mp, beta, N[6];
-              tn[0] = tang[(int64_t)qp * ne + e];
+              tn[0] = tq0[qp];
               if (tn[0] < T(-1.5)) {  // surrogate tangent of this point
                 const int slot = a.sur_map[(int64_t)qp * ne + e];
                 general_apply(H, static_cast<const T*>(a.sur_D) + (int64_t)slot * 36, S);
               } else {
-                if (tn[0] >= 0) {
 #pragma unroll
-                  for (int k = 1; k < 6; ++k) tn[k] = tang[(int64_t)(k * 8 + qp) * ne + e];
-                } else {
-#pragma unroll
-                  for (int k = 1; k < 6; ++k) tn[k] = 0;
-                }
+                for (int k = 1; k < 6; ++k) tn[k] = pw[qp & 1][k - 1];
                 j2_tangent_coeffs(tn, Kb, Gs, Hh, lp, mp, beta, N);
                 j2_apply(H, lp, mp, beta, N, S);
               }
