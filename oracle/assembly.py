@@ -20,7 +20,7 @@ from .mesh import element_dofs
 
 def assemble_vector(conn, r_e, n_dof):
     """R = sum_e A_e^T r_e."""
-    out = np.zeros(n_dof)
+    out = np.zeros(n_dof, dtype=np.result_type(r_e, np.float64))
     np.add.at(out, element_dofs(conn).ravel(), r_e.ravel())
     return out
 

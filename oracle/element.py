@@ -37,13 +37,16 @@ def residual_and_tangent(coords, conn, u, material, want_tangent=True):
     ue = u[element_dofs(conn)]
     pts, w = gauss_points()
     ne = len(conn)
-    r = np.zeros((ne, 24))
-    k = np.zeros((ne, 24, 24)) if want_tangent else None
+    r = k = None
     for q in range(8):
         dndx, det = physical_gradients(xe, pts[q])
         b = bmatrix(dndx)
         eps = np.einsum("eij,ej->ei", b, ue)
         sig, d = material(q, eps)
+        if r is None:  # real, or complex when a complex-step perturbation is carried
+            dt = np.result_type(sig, d, ue, np.float64)
+            r = np.zeros((ne, 24), dtype=dt)
+            k = np.zeros((ne, 24, 24), dtype=dt) if want_tangent else None
         wdet = w[q] * det
         r += np.einsum("eji,ej->ei", b, sig) * wdet[:, None]
         if want_tangent:
@@ -53,9 +56,9 @@ def residual_and_tangent(coords, conn, u, material, want_tangent=True):
 
 def linear_material(lam_e, mu_e):
     """Hooke's law per element with Lame parameters lam_e, mu_e (arrays over elements)."""
-    lam_e = np.asarray(lam_e, dtype=np.float64)
-    mu_e = np.asarray(mu_e, dtype=np.float64)
-    d = np.zeros((len(lam_e), 6, 6))
+    lam_e = np.asarray(lam_e)
+    mu_e = np.asarray(mu_e)
+    d = np.zeros((len(lam_e), 6, 6), dtype=np.result_type(lam_e, mu_e, np.float64))
     d[:, :3, :3] = lam_e[:, None, None]
     for i in range(3):
         d[:, i, i] += 2.0 * mu_e

@@ -19,6 +19,9 @@ starts from the last converged state (eps_p_n, alpha_n):
 Voigt conventions: strains [xx,yy,zz,yz,xz,xy] with engineering shears, stress
 with tensor components; I_sym -> diag(1,1,1,1/2,1/2,1/2), N x N uses tensor
 components of N.
+
+Every branch is decided on real parts, so complex inputs carry complex-step
+derivatives through unchanged (used by the path-adjoint oracle).
 """
 from __future__ import annotations
 
@@ -33,7 +36,7 @@ I_DEV = I_SYM - np.outer(ONE, ONE) / 3.0
 
 def strain_to_tensor(v):
     """(m,6) engineering Voigt strain -> (m,3,3) tensor."""
-    t = np.empty(v.shape[:-1] + (3, 3))
+    t = np.empty(v.shape[:-1] + (3, 3), dtype=np.result_type(v, np.float64))
     t[..., 0, 0], t[..., 1, 1], t[..., 2, 2] = v[..., 0], v[..., 1], v[..., 2]
     t[..., 1, 2] = t[..., 2, 1] = 0.5 * v[..., 3]
     t[..., 0, 2] = t[..., 2, 0] = 0.5 * v[..., 4]
@@ -55,7 +58,7 @@ def return_map(eps, eps_p_n, alpha_n, E, nu, sigma_y, H):
     plastic (m,) bool, f_trial (m,), dgamma (m,), q_trial (m,), N (m,6) tensor comps.
     """
     m = len(eps)
-    K, G = bulk_shear(np.broadcast_to(np.asarray(E, dtype=np.float64), (m,)), nu)
+    K, G = bulk_shear(np.broadcast_to(np.asarray(E), (m,)), nu)
     et = strain_to_tensor(eps - eps_p_n)
     tr = np.trace(et, axis1=-2, axis2=-1)
     eye = np.eye(3)
@@ -64,12 +67,12 @@ def return_map(eps, eps_p_n, alpha_n, E, nu, sigma_y, H):
     s_norm = np.sqrt(np.sum(s_tr * s_tr, axis=(-2, -1)))
     q_tr = np.sqrt(1.5) * s_norm
     f_tr = q_tr - (sigma_y + H * alpha_n)
-    plastic = f_tr > 0.0
+    plastic = np.real(f_tr) > 0.0  # real parts decide (complex-step derivatives pass through)
 
     dgam = np.where(plastic, f_tr / (3.0 * G + H), 0.0)
-    safe_norm = np.where(s_norm > 0.0, s_norm, 1.0)
+    safe_norm = np.where(np.real(s_norm) > 0.0, s_norm, 1.0)
     n_t = s_tr / safe_norm[:, None, None]
-    safe_q = np.where(q_tr > 0.0, q_tr, 1.0)
+    safe_q = np.where(np.real(q_tr) > 0.0, q_tr, 1.0)
     theta = np.where(plastic, 1.0 - 3.0 * G * dgam / safe_q, 1.0)
 
     sig_t = theta[:, None, None] * s_tr + p[:, None, None] * eye

@@ -56,7 +56,8 @@ class RVE:
 
     def _material(self, state_n, trial):
         ne = len(self.conn)
-        lam_e, mu_e = np.zeros(ne), np.zeros(ne)
+        lam_e = np.zeros(ne, dtype=np.result_type(self.scale, np.float64))
+        mu_e = np.zeros_like(lam_e)
         for pid, p in enumerate(self.phases):
             lam, mu = lame(p["E"], p["nu"])
             sel = self.phase == pid
@@ -89,9 +90,10 @@ class RVE:
         if state_n is None:
             state_n = self.zero_state()
         ne = len(self.conn)
-        trial = dict(eps_p=state_n["eps_p"].copy(), alpha=state_n["alpha"].copy(),
-                     plastic=np.zeros((ne, 8), dtype=bool), sigma=np.zeros((ne, 8, 6)),
-                     sigma_all=np.zeros((ne, 8, 6)))
+        dt = np.result_type(u, self.scale, state_n["eps_p"], np.float64)
+        trial = dict(eps_p=state_n["eps_p"].astype(dt), alpha=state_n["alpha"].astype(dt),
+                     plastic=np.zeros((ne, 8), dtype=bool), sigma=np.zeros((ne, 8, 6), dtype=dt),
+                     sigma_all=np.zeros((ne, 8, 6), dtype=dt))
         r_e, k_e = element.residual_and_tangent(self.coords, self.conn, u,
                                                 self._material(state_n, trial), want_tangent)
         nh_ids = [pid for pid, p in enumerate(self.phases) if p["model"] == "neohooke"]
