@@ -180,6 +180,22 @@ int fe_pcg(fe_problem* p, int op, const int32_t* row_ptr, const int32_t* col_idx
  * Neo-Hookean phases (r_e is proportional to s_e); FE_ERR_ARG with J2 phases. */
 int fe_vjp(fe_problem* p, const void* u, const void* lambda, void* out, void* stream);
 
+/* One backward step of the discrete adjoint through a J2 load path (history
+ * checkpointing, Sec. I's differentiable simulation through the path-dependent
+ * material).  FE_F64 problems with linear and J2 phases.  The step maps
+ * (u_n, h_{n-1}, s) to the residual R_n and the trial state h_n = Phi(u_n, h_{n-1}, s);
+ * given the linearisation point u (real [n_dof]) and the state at the start of
+ * the step state_in ([7][8][n_el], NULL = zero), and cotangents c on R_n (real
+ * [n_dof], NULL = 0) and mu_in on h_n ([7][8][n_el], NULL = 0), it writes
+ *   mu_out[7][8][n_el] = d(c.R_n + mu_in.h_n)/d h_{n-1}
+ * and accumulates (both optional, caller-zeroed)
+ *   u_bar[n_dof] += d(mu_in.h_n)/d u      (history part only: the adjoint right-hand side)
+ *   s_bar[n_el]  += d(c.R_n + mu_in.h_n)/d s_e.
+ * s is the per-element modulus scale of fe_set_materials (sigma_y, H unscaled).
+ * FE_ERR_ARG for FE_F32 problems or Neo-Hookean phases. */
+int fe_vjp_path(fe_problem* p, const void* u, const void* state_in, const void* c, const void* mu_in,
+                void* mu_out, void* u_bar, void* s_bar, void* stream);
+
 /* Newton load stepping: for each of n_steps macro strains (load_path_host:
  * [n_steps][3][3] row-major) lift the boundary, iterate Newton with the chosen
  * operator until the opts tolerance, then commit the plastic state.  Each

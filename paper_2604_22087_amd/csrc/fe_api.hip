@@ -577,6 +577,17 @@ extern "C" int fe_vjp(fe_problem* p, const void* u, const void* lambda, void* ou
   return FE_OK;
 }
 
+extern "C" int fe_vjp_path(fe_problem* p, const void* u, const void* state_in, const void* c, const void* mu_in,
+                           void* mu_out, void* u_bar, void* s_bar, void* stream) {
+  CHKP(p);
+  if (p->prec != FE_F64) return arg_error("fe_vjp_path needs an FE_F64 problem");
+  if (!p->materials_set) return arg_error("materials not set");
+  if (p->model_set == MS_NH) return arg_error("fe_vjp_path supports linear and J2 phases only");
+  if (!u || !mu_out) return arg_error("u and mu_out are required");
+  HIPCHK(launch_path_vjp(p, u, state_in, c, mu_in, mu_out, u_bar, s_bar, S(stream)));
+  return FE_OK;
+}
+
 extern "C" int fe_read_flags(fe_problem* p, int* flags, void* stream) {
   CHKP(p);
   if (!flags) return arg_error("flags is null");

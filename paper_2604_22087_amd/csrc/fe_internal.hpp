@@ -221,6 +221,9 @@ hipError_t launch_block_jacobi(const fe_problem* p, const int32_t* rp, const int
 inline void* pc_buffer(const fe_problem* p) { return p->precond == FE_PC_BLOCK_JACOBI ? p->w_blk : p->w_d; }
 
 hipError_t launch_lin_stats(const fe_problem* p, unsigned long long* out, hipStream_t s);
+// path adjoint through the return map (FP64 problems): see fe_vjp_path
+hipError_t launch_path_vjp(const fe_problem* p, const void* u, const void* hist, const void* c, const void* mu_in,
+                           void* mu_out, void* u_bar, void* s_bar, hipStream_t s);
 // network forward + Jacobian over a device-counted list (blocks beyond *count return)
 hipError_t launch_mlp_forward_counted(const float* W, const float* x, float* y, float* jac, int64_t cap,
                                       const unsigned int* count, hipStream_t s);

@@ -1900,6 +1900,175 @@ __global__ void lin_stats_kernel(int64_t ne, const uint8_t* phase, Phases mat, c
   }
 }
 
+// ---------------------------------------------------------------------------
+// Path adjoint through the return map (FP64).  Forward-mode dual numbers give the
+// Jacobian of one Gauss point's update (eps, eps_p_n, alpha_n, s) -> (sigma, eps_p,
+// alpha) column by column, from the same j2_update the residual uses; the
+// cotangents are contracted with it.
+
+struct Dual {
+  double v, d;
+  __device__ Dual(double x = 0.0, double y = 0.0) : v(x), d(y) {}
+  __device__ Dual& operator+=(Dual b) { v += b.v; d += b.d; return *this; }
+  __device__ Dual& operator-=(Dual b) { v -= b.v; d -= b.d; return *this; }
+};
+__device__ inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+__device__ inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+__device__ inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+__device__ inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+__device__ inline Dual operator/(Dual a, Dual b) { return Dual(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)); }
+__device__ inline Dual sqrt(Dual a) {
+  const double r = ::sqrt(a.v);
+  return Dual(r, r > 0.0 ? a.d / (2.0 * r) : 0.0);
+}
+__device__ inline bool operator>(Dual a, Dual b) { return a.v > b.v; }
+__device__ inline bool operator<(Dual a, Dual b) { return a.v < b.v; }
+__device__ inline bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
+
+struct PathArgs {
+  int n;
+  double h;
+  int64_t n_el;
+  const uint8_t* phase;
+  const double* scale;   // [n_el] or null (1)
+  Phases mat;
+  const double* u;       // linearisation displacement [n_dof]
+  const double* hist;    // state at the start of the step [7][8][n_el]
+  const double* c;       // cotangent of the residual [n_dof] or null
+  const double* mu_in;   // cotangent of the step's trial state [7][8][n_el] or null
+  double* mu_out;        // cotangent of the starting state [7][8][n_el] (written)
+  double* u_bar;         // += history part of the displacement cotangent [n_dof] or null
+  double* s_bar;         // += cotangent of the modulus scale [n_el] or null
+};
+
+__global__ __launch_bounds__(256) void path_vjp_kernel(PathArgs a) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= a.n_el) return;
+  const int n = a.n;
+  const int64_t ne = a.n_el, np1 = n + 1;
+  const int ea = (int)(e % n), eb = (int)((e / n) % n), ec = (int)(e / ((int64_t)n * n));
+  const double inv_h = 1.0 / a.h, w = 0.125 * a.h * a.h * a.h;
+  const PhaseConst pc = a.mat.ph[a.phase[e]];
+  const double sc = a.scale ? a.scale[e] : 1.0;
+  const bool j2 = pc.model == FE_J2;
+  double U[8][3], C[8][3], UB[8][3];
+  int64_t node[8];
+#pragma unroll
+  for (int l = 0; l < 8; ++l) {
+    node[l] = (ea + (l & 1)) + np1 * ((eb + ((l >> 1) & 1)) + np1 * (ec + (l >> 2)));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      U[l][c] = a.u[3 * node[l] + c];
+      C[l][c] = a.c ? a.c[3 * node[l] + c] : 0.0;
+      UB[l][c] = 0.0;
+    }
+  }
+  double sbar = 0.0;
+  for (int qp = 0; qp < 8; ++qp) {
+    const int p = qp & 1, q = (qp >> 1) & 1, r = qp >> 2;
+    double g[8][3];
+#pragma unroll
+    for (int l = 0; l < 8; ++l) basis_grad(l & 1, (l >> 1) & 1, l >> 2, p, q, r, inv_h, g[l]);
+    double H[3][3] = {}, Hc[3][3] = {};
+#pragma unroll
+    for (int l = 0; l < 8; ++l)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int J = 0; J < 3; ++J) {
+          H[c][J] += U[l][c] * g[l][J];
+          Hc[c][J] += C[l][c] * g[l][J];
+        }
+    // stress cotangent: c . R = sum_q w (B_q c_e) . sigma_q (engineering-shear pairing)
+    const double sb[6] = {w * Hc[0][0], w * Hc[1][1], w * Hc[2][2], w * (Hc[1][2] + Hc[2][1]),
+                          w * (Hc[0][2] + Hc[2][0]), w * (Hc[0][1] + Hc[1][0])};
+    double mu[7], ebar[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 7; ++k) mu[k] = a.mu_in ? a.mu_in[(int64_t)(k * 8 + qp) * ne + e] : 0.0;
+    if (j2) {
+      double hn[7];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) hn[k] = a.hist ? a.hist[(int64_t)(k * 8 + qp) * ne + e] : 0.0;
+      for (int col = 0; col < 14; ++col) {
+        Dual Hd[3][3], epd[6], ad, Kd(pc.K * sc), Gd(pc.G * sc);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) Hd[i][j] = Dual(H[i][j]);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) epd[k] = Dual(hn[k]);
+        ad = Dual(hn[6]);
+        if (col < 3) {
+          Hd[col][col].d = 1.0;
+        } else if (col < 6) {  // engineering shear strain: half to each off-diagonal entry
+          const int i = col == 3 ? 1 : 0, j = col == 5 ? 1 : 2;
+          Hd[i][j].d = 0.5;
+          Hd[j][i].d = 0.5;
+        } else if (col < 12) {
+          epd[col - 6].d = 1.0;
+        } else if (col == 12) {
+          ad.d = 1.0;
+        } else {
+          Kd.d = pc.K;
+          Gd.d = pc.G;
+        }
+        Dual S[3][3], ep[6], al, tn[6];
+        j2_update(Hd, epd, ad, Kd, Gd, Dual(pc.sy), Dual(pc.H), S, ep, al, tn);
+        const double hon = mu[0] * ep[0].d + mu[1] * ep[1].d + mu[2] * ep[2].d + mu[3] * ep[3].d +
+                           mu[4] * ep[4].d + mu[5] * ep[5].d + mu[6] * al.d;
+        const double tot = hon + sb[0] * S[0][0].d + sb[1] * S[1][1].d + sb[2] * S[2][2].d + sb[3] * S[1][2].d +
+                           sb[4] * S[0][2].d + sb[5] * S[0][1].d;
+        if (col < 6)
+          ebar[col] = hon;
+        else if (col < 13)
+          a.mu_out[(int64_t)((col - 6) * 8 + qp) * ne + e] = tot;
+        else
+          sbar += tot;
+      }
+    } else {  // history-free phase: the state passes through; sigma = s D_hat eps
+      double S[3][3];
+      hooke(H, pc.lam, pc.mu, S);
+      sbar += sb[0] * S[0][0] + sb[1] * S[1][1] + sb[2] * S[2][2] + sb[3] * S[1][2] + sb[4] * S[0][2] +
+              sb[5] * S[0][1];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) a.mu_out[(int64_t)(k * 8 + qp) * ne + e] = mu[k];
+    }
+    if (a.u_bar && j2) {  // d/dH of the engineering strain: symmetric split of the shear entries
+      const double Hb[3][3] = {{ebar[0], ebar[5], ebar[4]}, {ebar[5], ebar[1], ebar[3]}, {ebar[4], ebar[3], ebar[2]}};
+#pragma unroll
+      for (int l = 0; l < 8; ++l)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) UB[l][c] += Hb[c][0] * g[l][0] + Hb[c][1] * g[l][1] + Hb[c][2] * g[l][2];
+    }
+  }
+  if (a.s_bar) a.s_bar[e] += sbar;
+  if (a.u_bar)
+#pragma unroll
+    for (int l = 0; l < 8; ++l)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) atomic_add(a.u_bar + 3 * node[l] + c, UB[l][c]);
+}
+
+hipError_t launch_path_vjp(const fe_problem* p, const void* u, const void* hist, const void* c, const void* mu_in,
+                           void* mu_out, void* u_bar, void* s_bar, hipStream_t s) {
+  PathArgs a;
+  a.n = p->n;
+  a.h = p->h;
+  a.n_el = p->n_el;
+  a.phase = p->phase;
+  a.scale = static_cast<const double*>(p->scale);
+  a.mat = p->mat;
+  a.u = static_cast<const double*>(u);
+  a.hist = static_cast<const double*>(hist);
+  a.c = static_cast<const double*>(c);
+  a.mu_in = static_cast<const double*>(mu_in);
+  a.mu_out = static_cast<double*>(mu_out);
+  a.u_bar = static_cast<double*>(u_bar);
+  a.s_bar = static_cast<double*>(s_bar);
+  hipLaunchKernelGGL(path_vjp_kernel, dim3((unsigned)((p->n_el + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_lin_stats(const fe_problem* p, unsigned long long* out, hipStream_t s) {
   const dim3 g((unsigned)((p->n_el + 255) / 256)), b(256);
   if (p->prec == FE_F64)

@@ -60,6 +60,7 @@ SIGNATURES = [
     ("fe_apply_csr", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("fe_diagonal", _i32, [_vp, _vp, _i32, _vp]),
     ("fe_set_preconditioner", _i32, [_vp, _i32]),
+    ("fe_vjp_path", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("fe_pcg", _i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _dbl, _i32, ctypes.POINTER(PcgInfo), _vp]),
     ("fe_vjp", _i32, [_vp, _vp, _vp, _vp, _vp]),
     ("fe_newton", _i32, [_vp, ctypes.POINTER(_dbl), _i32, ctypes.POINTER(NewtonOpts), _vp, _vp,
@@ -262,6 +263,20 @@ class Problem:
             self._real(out, self.n_el, "out")
         _check(self.lib.fe_vjp(self.handle, _ptr(u), _ptr(lam), _ptr(out), _stream()), "fe_vjp")
         return out
+
+    def vjp_path(self, u, state_in, c=None, mu_in=None, mu_out=None, u_bar=None, s_bar=None):
+        """One backward step through the return map (FP64): writes mu_out = d(c.R + mu_in.h)/d h_in,
+        accumulates u_bar += d(mu_in.h)/du and s_bar += d(c.R + mu_in.h)/ds.  Returns mu_out."""
+        self._real(u, self.n_dof, "u")
+        mu_out = self.state() if mu_out is None else self._real(mu_out, 56 * self.n_el, "mu_out")
+        for t, size, name in ((state_in, 56 * self.n_el, "state_in"), (c, self.n_dof, "c"),
+                              (mu_in, 56 * self.n_el, "mu_in"), (u_bar, self.n_dof, "u_bar"),
+                              (s_bar, self.n_el, "s_bar")):
+            if t is not None:
+                self._real(t, size, name)
+        _check(self.lib.fe_vjp_path(self.handle, _ptr(u), _ptr(state_in), _ptr(c), _ptr(mu_in), _ptr(mu_out),
+                                    _ptr(u_bar), _ptr(s_bar), _stream()), "fe_vjp_path")
+        return mu_out
 
     def newton(self, load_path, u=None, state=None, op=OP_MATFREE, max_newton=20, newton_rtol=1e-8,
                pcg_rtol=1e-10, pcg_max_it=100000, assemble_csr=False, check=True):
