@@ -210,6 +210,38 @@ def surrogate_leg(n):
     return out
 
 
+def adjoint_path_leg(n):
+    """Adjoint through a plastic load path: n^3 fiber RVE (J2 matrix, per-element modulus scale
+    U(0.8, 1.2), seed 5), non-proportional path (tension 0.012, then shear 0.008 added, then tension
+    relaxed to 0.004 with shear 0.012), reaction work after the last step and its gradient with
+    respect to every element's modulus scale (history checkpointed per step)."""
+    import torch
+    from paper_2604_22087_amd import fe, inputs
+    from paper_2604_22087_amd.adjoint import ReactionWorkPath
+
+    def strain(xx, xy):
+        return np.array([[xx, xy, 0.0], [xy, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    path = [strain(0.012, 0.0), strain(0.012, 0.008), strain(0.004, 0.012)]
+    phase = inputs.fiber_phase(n, n_fibers=64, radius=0.05, seed=2)
+    s = torch.tensor(inputs.uniform_field(n ** 3, 0.8, 1.2, seed=5), device="cuda", requires_grad=True)
+    P = fe.Problem(n, "f64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = ReactionWorkPath.apply(s, P, torch.tensor(phase, device="cuda"), [fe.J2, fe.LINEAR],
+                               [MATRIX, FIBER + (0.0, 0.0)], torch.tensor(inputs.boundary_dof_mask(n), device="cuda"),
+                               path, 1e-10, 1e-12)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g = s.grad.double()
+    return {"workload": f"{n}^3 fiber RVE, 3-step non-proportional path, dJ/ds for {n ** 3} elements",
+            "J": float(J.detach()), "forward_seconds": t1 - t0, "backward_seconds": t2 - t1,
+            "grad_norm": float(torch.linalg.norm(g)), "grad_min": float(g.min()), "grad_max": float(g.max()),
+            "checkpoint_bytes": 3 * (56 * P.n_el + P.n_dof) * 8}
+
+
 def cpu_baseline(n, phase, gpu_info, path):
     """The FP64 oracle on a bounded sample of the same workload (host cores)."""
     from oracle import solver
@@ -250,6 +282,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 ramp")
     ap.add_argument("--nh", type=int, default=0, help="also run the finite-strain Neo-Hookean leg at this n (0: skip)")
     ap.add_argument("--surrogate", type=int, default=96, help="n of the surrogate-vs-return-map leg (0: skip)")
+    ap.add_argument("--adjoint-path", type=int, default=64, help="n of the plastic-path adjoint leg (0: skip)")
     ap.add_argument("--copy-calib", action="store_true", help="run only a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -343,6 +376,9 @@ def main():
     if args.surrogate:
         print(f"[bench] surrogate leg {args.surrogate}^3", file=sys.stderr, flush=True)
         out["surrogate"] = surrogate_leg(args.surrogate)
+    if args.adjoint_path:
+        print(f"[bench] adjoint path leg {args.adjoint_path}^3", file=sys.stderr, flush=True)
+        out["adjoint_path"] = adjoint_path_leg(args.adjoint_path)
     if args.nh:
         print(f"[bench] neo-hookean leg {args.nh}^3", file=sys.stderr, flush=True)
         out["neohooke"] = neohooke_leg(args.nh)
