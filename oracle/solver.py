@@ -118,3 +118,59 @@ def pcg(apply_a, diag, b, rtol, max_it, precond=None):
         rz = rz_new
     true_rel = np.linalg.norm(b - apply_a(x)) / bnorm
     return x, it, status, true_rel
+
+
+def bicgstab(apply_a, b, rtol, max_it, precond=None):
+    """Right-preconditioned BiCGStab (van der Vorst 1992; Saad, Iterative Methods for
+    Sparse Linear Systems, 2003, Alg. 7.7) for nonsymmetric operators, x0 = 0,
+    shadow residual r_hat = r0.  Stops when ||r||_2 <= rtol ||b||_2 (checked on the
+    half-step residual s as well).  One iteration = two operator applications.
+    Returns (x, iterations, status, true relative residual)."""
+    minv = precond if precond is not None else (lambda v: v)
+    x = np.zeros_like(b)
+    r = b.copy()
+    bnorm = np.linalg.norm(b)
+    if not np.all(np.isfinite(b)):
+        return x, 0, NONFINITE, np.nan
+    if bnorm == 0.0:
+        return x, 0, OK, 0.0
+    r_hat = r.copy()
+    rho_old = alpha = omega = 1.0
+    v = np.zeros_like(b)
+    p = np.zeros_like(b)
+    status, it = NOT_CONVERGED, 0
+    while it < max_it:
+        rho = r_hat @ r
+        if rho == 0.0 or omega == 0.0:
+            status = BREAKDOWN
+            break
+        beta = (rho / rho_old) * (alpha / omega)
+        p = r + beta * (p - omega * v)
+        p_hat = minv(p)
+        v = apply_a(p_hat)
+        rv = r_hat @ v
+        if rv == 0.0 or not np.isfinite(rv):
+            status = BREAKDOWN if np.isfinite(rv) else NONFINITE
+            break
+        alpha = rho / rv
+        s = r - alpha * v
+        it += 1
+        if np.linalg.norm(s) <= rtol * bnorm:
+            x += alpha * p_hat
+            status = OK
+            break
+        s_hat = minv(s)
+        t = apply_a(s_hat)
+        tt = t @ t
+        omega = (t @ s) / tt if tt > 0.0 else 0.0
+        x += alpha * p_hat + omega * s_hat
+        r = s - omega * t
+        rho_old = rho
+        if not np.all(np.isfinite(r)):
+            status = NONFINITE
+            break
+        if np.linalg.norm(r) <= rtol * bnorm:
+            status = OK
+            break
+    true_rel = np.linalg.norm(b - apply_a(x)) / bnorm
+    return x, it, status, true_rel

@@ -226,3 +226,32 @@ def test_block_jacobi_pcg_special_cases():
     x, it, status, rel = solver.pcg(lambda p: solver.matfree_apply(conn, k, p, mask), None, b, 1e-14, 1000, precond=pre)
     assert status == solver.OK and rel <= 1e-13
     assert np.linalg.norm(x - x_ref) <= 1e-12 * np.linalg.norm(x_ref)
+
+
+def test_bicgstab_nonsymmetric_and_spd():
+    """BiCGStab against a dense library solve: a nonsymmetric diagonally dominant
+    matrix (with and without Jacobi preconditioning) and the SPD config-1-type
+    operator, where it must reach the same solution as CG."""
+    rng = np.random.default_rng(9)
+    m = 60
+    a = rng.normal(size=(m, m)) + 12.0 * np.eye(m)
+    b = rng.normal(size=m)
+    x_ref = np.linalg.solve(a, b)
+    for pre in (None, lambda v: v / np.diag(a)):
+        x, it, status, rel = solver.bicgstab(lambda v: a @ v, b, 1e-13, 500, precond=pre)
+        assert status == solver.OK and rel <= 1e-12
+        assert np.linalg.norm(x - x_ref) <= 1e-11 * np.linalg.norm(x_ref)
+    n = 3
+    coords, conn, k = _two_phase_tangents(n, seed=11)
+    ndof = 3 * len(coords)
+    mask = inputs.boundary_dof_mask(n)
+    rp, ci, v = assembly.assemble_csr(conn, k, ndof)
+    vb = assembly.dirichlet_csr(rp, ci, v, mask)
+    dense = np.zeros((ndof, ndof))
+    dense[assembly.csr_rows(rp), ci] = vb
+    b = RNG.normal(size=ndof) * (1 - mask)
+    d = assembly.csr_diagonal(rp, ci, vb)
+    x, it, status, rel = solver.bicgstab(lambda p: assembly.csr_matvec(rp, ci, vb, p), b, 1e-14, 1000,
+                                         precond=lambda r: r / d)
+    assert status == solver.OK and rel <= 1e-13
+    assert np.linalg.norm(x - np.linalg.solve(dense, b)) <= 1e-12 * np.linalg.norm(x)
