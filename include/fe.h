@@ -61,6 +61,7 @@ enum { FE_F64 = 0, FE_F32 = 1 };                      /* precision of real array
 enum { FE_LINEAR = 0, FE_J2 = 1, FE_NEOHOOKE = 2 };    /* constitutive model per phase */
 enum { FE_OP_CSR = 0, FE_OP_MATFREE = 1 };             /* operator used by fe_pcg / fe_newton */
 enum { FE_PC_JACOBI = 0, FE_PC_BLOCK_JACOBI = 1 };     /* CG preconditioner (fe_set_preconditioner) */
+enum { FE_SOLVER_CG = 0, FE_SOLVER_BICGSTAB = 1 };     /* Krylov method of fe_newton's inner solves */
 enum { FE_APPLY_BC = 1, FE_STORE_TANGENT = 2 };        /* fe_residual flags */
 enum { FE_MAX_PHASES = 8 };
 
@@ -82,6 +83,7 @@ typedef struct {
   double newton_rtol;    /* stop when ||P_f R|| <= newton_rtol * ||P_f R||_first (e.g. 1e-8) */
   double pcg_rtol;       /* inner CG tolerance (e.g. 1e-10) */
   int pcg_max_it;        /* inner CG iteration limit */
+  int solver;            /* FE_SOLVER_CG (symmetric tangents) or FE_SOLVER_BICGSTAB */
 } fe_newton_opts;
 
 typedef struct {
@@ -174,6 +176,16 @@ int fe_set_preconditioner(fe_problem* p, int kind);
 int fe_pcg(fe_problem* p, int op, const int32_t* row_ptr, const int32_t* col_idx,
            const void* vals, const void* b, void* x, double rtol, int max_it,
            fe_pcg_info* info_host, void* stream);
+
+/* Preconditioned BiCGStab on A x = b for nonsymmetric operators (the paper's
+ * Fig. 4 compares CG, GMRES and BiCGStab): same operators, arguments,
+ * preconditioner (fe_set_preconditioner) and stopping rule as fe_pcg; one
+ * iteration applies A twice.  Returns FE_OK, FE_ERR_NOT_CONVERGED,
+ * FE_ERR_BREAKDOWN (rho or (r_hat, v) vanished) or FE_ERR_NONFINITE.  Workspace of
+ * 8 vectors allocated on first use (FE_ERR_OOM if that fails). */
+int fe_bicgstab(fe_problem* p, int op, const int32_t* row_ptr, const int32_t* col_idx,
+                const void* vals, const void* b, void* x, double rtol, int max_it,
+                fe_pcg_info* info_host, void* stream);
 
 /* Vector-Jacobian product with respect to the per-element modulus scale s_e:
  * out[e] = lambda_e^T d r_e / d s_e, real [n_el].  Supported for linear and
@@ -276,6 +288,12 @@ int fe_adam_step(float* W, const float* dW, float* m, float* v, int64_t n_param,
  * Every fe_residual then runs three launches (list plastic-trial points,
  * network, residual) and synchronises once. */
 int fe_set_surrogate(fe_problem* p, const float* W, double fallback_tol);
+
+/* Tangent handed to the linear solver at accepted surrogate points: 0 (default)
+ * the symmetric part of the network Jacobian (for CG), 1 the Jacobian itself,
+ * which makes the operator nonsymmetric (solve with FE_SOLVER_BICGSTAB /
+ * fe_bicgstab).  Takes effect at the next residual evaluation. */
+int fe_set_surrogate_tangent(fe_problem* p, int full);
 
 /* After fe_residual with a surrogate: out_host = {points given to the network,
  * accepted, fallbacks} (synchronises). */

@@ -134,6 +134,9 @@ void fe_problem_destroy(fe_problem* p) {
   free_dev(p->w_q);
   free_dev(p->w_d);
   free_dev(p->w_blk);
+  free_dev(p->w_bicg);
+  free_dev(p->bicg_part);
+  free_dev(p->bicg_ctrl);
   free_dev(p->w_v);
   free_dev(p->w_v2);
   free_dev(p->w_state);
@@ -368,6 +371,7 @@ static int residual_impl(fe_problem* p, const void* u, const void* state_in, voi
     a.sur_D = p->sur_D;
     a.sur_stats = p->sur_count + 1;
     a.sur_tol = p->sur_tol;
+    a.sur_full = p->sur_full;
   } else if (j2 && p->cap_x) {
     a.sur_mode = SUR_CAPTURE;
     a.sur_count = p->cap_count;
@@ -483,6 +487,13 @@ int fe_diagonal(fe_problem* p, void* d, int apply_bc, void* stream) {
   return FE_OK;
 }
 
+int fe_set_surrogate_tangent(fe_problem* p, int full) {
+  CHKP(p);
+  if (full != 0 && full != 1) return arg_error("full must be 0 or 1");
+  p->sur_full = full;
+  return FE_OK;
+}
+
 int fe_set_preconditioner(fe_problem* p, int kind) {
   CHKP(p);
   if (kind != FE_PC_JACOBI && kind != FE_PC_BLOCK_JACOBI) return arg_error("kind must be FE_PC_JACOBI or FE_PC_BLOCK_JACOBI");
@@ -548,6 +559,84 @@ static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, 
   if (applies) *applies += c.iters + (status == FE_ERR_BREAKDOWN || status == FE_ERR_NONFINITE ? 1 : 0);
   if (status != FE_OK) set_error(fe_status_string(status));
   return status;
+}
+
+// Preconditioned BiCGStab driver (same preconditioner set-up and polling as pcg_run).
+static int bicg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, const void* b,
+                    void* x, double rtol, int max_it, fe_pcg_info* info, hipStream_t s, int* applies) {
+  const size_t rs = real_size(p);
+  if (!p->w_bicg && alloc(&p->w_bicg, 8 * rs * (size_t)p->n_dof)) return FE_ERR_OOM;
+  if (!p->bicg_part && alloc((void**)&p->bicg_part, 6 * BICG_GRID * sizeof(double))) return FE_ERR_OOM;
+  if (!p->bicg_ctrl && alloc((void**)&p->bicg_ctrl, sizeof(BicgCtrl))) return FE_ERR_OOM;
+  if (p->precond == FE_PC_BLOCK_JACOBI) {
+    HIPCHK(launch_block_jacobi(p, rp, ci, vals, p->w_blk, s));
+  } else if (rp) {
+    HIPCHK(launch_csr_diag(p, rp, ci, vals, p->w_d, s));
+  } else {
+    HIPCHK(launch_diag(p, p->w_d, 1, s));
+  }
+  HIPCHK(bicg_init(p, b, x, rtol, max_it, s));
+  const int* stop = &p->bicg_ctrl->status;
+  char* base = static_cast<char*>(p->w_bicg);
+  void* v = base + 3 * rs * p->n_dof;
+  void* t = base + 5 * rs * p->n_dof;
+  void* ph = base + 6 * rs * p->n_dof;
+  void* sh = base + 7 * rs * p->n_dof;
+  auto apply = [&](const void* in, void* out) -> hipError_t {
+    if (op == FE_OP_CSR) return launch_spmv_stop(p, rp, ci, vals, in, out, stop, s);
+    ElemArgs a = base_args(p);
+    a.x = in;
+    a.xlin = p->u_lin;
+    a.y = out;
+    a.apply_bc = 1;
+    return launch_elem_stop(p, OP_APPLY, a, stop, s);
+  };
+  BicgCtrl* hc = reinterpret_cast<BicgCtrl*>(p->host_buf);
+  static_assert(sizeof(BicgCtrl) <= 64 * sizeof(double), "host scratch too small");
+  int launched = 0, chunk = 4;
+  for (;;) {
+    for (int c = 0; c < chunk; ++c) {
+      HIPCHK(bicg_step(p, 0, x, s));  // direction
+      HIPCHK(apply(ph, v));
+      HIPCHK(bicg_step(p, 4, x, s));  // (r_hat, v)
+      HIPCHK(bicg_step(p, 1, x, s));  // half step
+      HIPCHK(apply(sh, t));
+      HIPCHK(bicg_step(p, 2, x, s));  // (t, s), (t, t)
+      HIPCHK(bicg_step(p, 3, x, s));  // update
+    }
+    launched += chunk;
+    HIPCHK(hipMemcpyAsync(hc, p->bicg_ctrl, sizeof(BicgCtrl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hc->status != CG_RUNNING || hc->finish || launched > max_it + 16) break;
+    if (chunk < 16) chunk *= 2;
+  }
+  const int status = hc->finish ? FE_OK
+                     : (hc->status == CG_RUNNING ? FE_ERR_NOT_CONVERGED
+                                                 : (hc->status == CG_CONVERGED ? FE_OK : hc->status));
+  if (info) {
+    info->iterations = hc->iters;
+    info->status = status;
+    info->bnorm = std::sqrt(hc->bb);
+    info->relres = hc->bb > 0 ? std::sqrt(hc->rr / hc->bb) : 0.0;
+  }
+  if (applies) *applies += 2 * hc->iters;
+  if (status != FE_OK) set_error(fe_status_string(status));
+  return status;
+}
+
+extern "C" int fe_bicgstab(fe_problem* p, int op, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
+                           const void* b, void* x, double rtol, int max_it, fe_pcg_info* info, void* stream) {
+  CHKP(p);
+  if (!b || !x) return arg_error("b and x are required");
+  if (op != FE_OP_CSR && op != FE_OP_MATFREE) return arg_error("op must be FE_OP_CSR or FE_OP_MATFREE");
+  if (op == FE_OP_CSR && (!row_ptr || !col_idx || !vals)) return arg_error("CSR operator needs row_ptr, col_idx, vals");
+  if (op == FE_OP_MATFREE && !p->lin_valid) {
+    set_error("no linearisation stored");
+    return FE_ERR_STATE;
+  }
+  if (!(rtol >= 0) || max_it < 0) return arg_error("rtol must be >= 0 and max_it >= 0");
+  if (op == FE_OP_MATFREE) row_ptr = nullptr, col_idx = nullptr, vals = nullptr;
+  return bicg_run(p, op, row_ptr, col_idx, vals, b, x, rtol, max_it, info, S(stream), nullptr);
 }
 
 extern "C" int fe_pcg(fe_problem* p, int op, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
@@ -679,7 +768,9 @@ extern "C" int fe_newton(fe_problem* p, const double* path, int n_steps, const f
         vals = p->csr_v;
       }
       fe_pcg_info pi{};
-      st = pcg_run(p, o->op, rp, ci, vals, r, w, o->pcg_rtol, o->pcg_max_it, &pi, s, &inf.operator_applies);
+      st = o->solver == FE_SOLVER_BICGSTAB
+               ? bicg_run(p, o->op, rp, ci, vals, r, w, o->pcg_rtol, o->pcg_max_it, &pi, s, &inf.operator_applies)
+               : pcg_run(p, o->op, rp, ci, vals, r, w, o->pcg_rtol, o->pcg_max_it, &pi, s, &inf.operator_applies);
       inf.pcg_iterations += pi.iterations;
       if (st) {
         inf.status = st;

@@ -63,6 +63,16 @@ struct CgCtrl {
   int pad;
 };
 
+// Device scalar block of BiCGStab (one per problem).
+struct BicgCtrl {
+  double rho, rho_old, alpha, omega, beta;
+  double rr;        // ||r||^2 at the last check
+  double bb, tol2, rtol2;
+  int iters, status, max_it;
+  int finish;       // set by the update that met the tolerance; the next direction step stops
+};
+constexpr int BICG_GRID = 512;       // workgroups of the BiCGStab vector kernels (= partial slots)
+
 struct ElemArgs {
   int n;
   double h;
@@ -94,6 +104,7 @@ struct ElemArgs {
   unsigned int* sur_stats;// [2] accepted, fallback
   float sur_sin, sur_sout;
   double sur_tol;
+  int sur_full;           // 1: the network Jacobian as tangent (nonsymmetric), 0: its symmetric part
   unsigned int sur_stride, sur_salt;
   // OP_CG_APPLY only
   const void* cg_r;       // residual r
@@ -134,6 +145,9 @@ struct fe_problem {
   void* w_d = nullptr;        // inverse diagonal
   int precond = FE_PC_JACOBI; // FE_PC_JACOBI or FE_PC_BLOCK_JACOBI
   void* w_blk = nullptr;      // inverse node blocks [n_nodes][6] (allocated on first use)
+  void* w_bicg = nullptr;     // BiCGStab vectors r, r_hat, p, v, s, t, p_hat, s_hat (allocated on first use)
+  double* bicg_part = nullptr;  // BiCGStab partial sums [8][BICG_GRID]
+  fe::BicgCtrl* bicg_ctrl = nullptr;
   void* w_v = nullptr;        // scratch vector (Newton)
   void* w_v2 = nullptr;       // scratch vector (Newton)
   void* w_state = nullptr;    // J2 trial state (Newton)
@@ -151,6 +165,7 @@ struct fe_problem {
   int64_t n_j2_el = 0;              // elements of J2 phases
   const float* sur_W = nullptr;     // network parameters (caller-owned)
   double sur_tol = 0;
+  int sur_full = 0;                 // fe_set_surrogate_tangent
   int64_t sur_cap = 0;
   int* sur_map = nullptr;
   float* sur_x = nullptr;
@@ -221,6 +236,14 @@ hipError_t launch_block_jacobi(const fe_problem* p, const int32_t* rp, const int
 inline void* pc_buffer(const fe_problem* p) { return p->precond == FE_PC_BLOCK_JACOBI ? p->w_blk : p->w_d; }
 
 hipError_t launch_lin_stats(const fe_problem* p, unsigned long long* out, hipStream_t s);
+// element / CSR operator launches that return at once while *stop is set (BiCGStab)
+hipError_t launch_elem_stop(const fe_problem* p, int op, const ElemArgs& a, const int* stop, hipStream_t s);
+hipError_t launch_spmv_stop(const fe_problem* p, const int32_t* rp, const int32_t* ci, const void* v,
+                            const void* x, void* y, const int* stop, hipStream_t s);
+// BiCGStab pieces (see the kernels): init, then per iteration
+//   bicg_dir, A p_hat -> v, bicg_half, A s_hat -> t, bicg_dots, bicg_update
+hipError_t bicg_init(const fe_problem* p, const void* b, void* x, double rtol, int max_it, hipStream_t s);
+hipError_t bicg_step(const fe_problem* p, int stage, void* x, hipStream_t s);
 // path adjoint through the return map (FP64 problems): see fe_vjp_path
 hipError_t launch_path_vjp(const fe_problem* p, const void* u, const void* hist, const void* c, const void* mu_in,
                            void* mu_out, void* u_bar, void* s_bar, hipStream_t s);

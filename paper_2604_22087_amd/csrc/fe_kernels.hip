@@ -383,7 +383,7 @@ __device__ __forceinline__ void sur_inputs(const T H[3][3], const T epn[6], T an
 template <typename T>
 __device__ __forceinline__ bool sur_consume(const T H[3][3], const T epn[6], T an, T K, T G, T sy, T Hh,
                                             const float* y, const float* J, float s_in, float s_out, double tol,
-                                            const T tn[6], T S[3][3], T ep[6], T& al, T* Dsym) {
+                                            const T tn[6], T S[3][3], T ep[6], T& al, T* Dsym, int full) {
   const T c[6] = {T(1), T(1), T(1), T(RSQ2), T(RSQ2), T(RSQ2)};
   T sig[6];
 #pragma unroll
@@ -424,7 +424,9 @@ __device__ __forceinline__ bool sur_consume(const T H[3][3], const T epn[6], T a
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
-    for (int j = 0; j < 6; ++j) Dsym[i * 6 + j] = T(0.5) * f * c[i] * c[j] * (T(J[i * 6 + j]) + T(J[j * 6 + i]));
+    for (int j = 0; j < 6; ++j)
+      Dsym[i * 6 + j] = full ? f * c[i] * c[j] * T(J[i * 6 + j])
+                             : T(0.5) * f * c[i] * c[j] * (T(J[i * 6 + j]) + T(J[j * 6 + i]));
   return true;
 }
 
@@ -719,7 +721,7 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
                     T* Dsym = static_cast<T*>(a.sur_D) + (int64_t)slot * 36;
                     accepted = sur_consume(H, epn, an, Kb, Gs, sy, Hh, a.sur_y + (int64_t)slot * 6,
                                            a.sur_jac + (int64_t)slot * 36, a.sur_sin, a.sur_sout, a.sur_tol, tn,
-                                           Ss, eps2, al2, Dsym);
+                                           Ss, eps2, al2, Dsym, a.sur_full);
                     fallback = !accepted;
                     if (accepted) {
 #pragma unroll
@@ -949,6 +951,10 @@ static hipError_t launch_elem_op(const fe_problem* p, int op, const ElemArgs& a,
   if (op == OP_RESID) return launch_elem_t<T, OP_RESID>(p, a, stop, s);
   if (op == OP_APPLY) return launch_elem_t<T, OP_APPLY>(p, a, stop, s);
   return launch_elem_t<T, OP_VJP>(p, a, stop, s);
+}
+
+hipError_t launch_elem_stop(const fe_problem* p, int op, const ElemArgs& a, const int* stop, hipStream_t s) {
+  return p->prec == FE_F64 ? launch_elem_op<double>(p, op, a, stop, s) : launch_elem_op<float>(p, op, a, stop, s);
 }
 
 hipError_t launch_elem(const fe_problem* p, int op, const ElemArgs& a, hipStream_t s) {
@@ -1332,6 +1338,12 @@ hipError_t launch_spmv(const fe_problem* p, const int32_t* rp, const int32_t* ci
                        void* y, hipStream_t s) {
   return p->prec == FE_F64 ? launch_spmv_t(p, rp, ci, (const double*)v, (const double*)x, (double*)y, nullptr, s)
                            : launch_spmv_t(p, rp, ci, (const float*)v, (const float*)x, (float*)y, nullptr, s);
+}
+
+hipError_t launch_spmv_stop(const fe_problem* p, const int32_t* rp, const int32_t* ci, const void* v,
+                            const void* x, void* y, const int* stop, hipStream_t s) {
+  return p->prec == FE_F64 ? launch_spmv_t(p, rp, ci, (const double*)v, (const double*)x, (double*)y, stop, s)
+                           : launch_spmv_t(p, rp, ci, (const float*)v, (const float*)x, (float*)y, stop, s);
 }
 
 // Diagonal of a CSR matrix with sorted columns (binary search per row).
@@ -1898,6 +1910,255 @@ __global__ void lin_stats_kernel(int64_t ne, const uint8_t* phase, Phases mat, c
     atomicAdd(out, cnt);
     atomicAdd(out + 1, pl);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioned BiCGStab (nonsymmetric operators) with device-resident scalars.
+// Vector kernels write per-workgroup partial sums; the next vector kernel reduces
+// them redundantly in every workgroup (same order, same result) and workgroup 0
+// records the scalars.  Per iteration:
+//   DIR:    rho = (r_hat, r); stop test on ||r||; p = r + beta (p - omega v); p_hat = M^-1 p; v = 0
+//   (operator) v = A p_hat
+//   HALF:   alpha = rho / (r_hat, v); s = r - alpha v; s_hat = M^-1 s; partial ||s||^2
+//   (operator) t = A s_hat
+//   DOTS:   partials of (t, s), (t, t)
+//   UPDATE: ||s|| small: x += alpha p_hat, stop; else omega = (t,s)/(t,t),
+//           x += alpha p_hat + omega s_hat, r = s - omega t, t = 0; partials (r_hat, r), ||r||^2
+// Partial slots: 0 (r_hat, r), 1 ||r||^2, 2 (r_hat, v), 3 ||s||^2, 4 (t, s), 5 (t, t).
+
+enum { BICG_DIR = 0, BICG_HALF = 1, BICG_DOTS = 2, BICG_UPDATE = 3 };
+
+template <typename T> struct BicgVec {
+  T *x, *r, *rh, *p, *v, *sv, *t, *ph, *sh;
+  const T* M;
+  int block;
+};
+
+// dst[node] = M^-1 v for one node (point Jacobi: inverse diagonal; node blocks: symmetric 3x3 inverse)
+template <typename T>
+__device__ __forceinline__ void bicg_precond(const BicgVec<T>& w, int64_t nd, const T v[3], T* dst) {
+  if (w.block) {
+    const T* m = w.M + 6 * nd;
+    dst[3 * nd] = m[0] * v[0] + m[5] * v[1] + m[4] * v[2];
+    dst[3 * nd + 1] = m[5] * v[0] + m[1] * v[1] + m[3] * v[2];
+    dst[3 * nd + 2] = m[4] * v[0] + m[3] * v[1] + m[2] * v[2];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dst[3 * nd + c] = w.M[3 * nd + c] * v[c];
+  }
+}
+
+__device__ __forceinline__ double bicg_sum(const double* part, int slot, double* sh, double* bc) {
+  return sum_partials_all(part + (int64_t)slot * BICG_GRID, BICG_GRID, sh, bc);
+}
+
+template <typename T>
+__global__ __launch_bounds__(VBLOCK) void bicg_kernel(int stage, int64_t n, BicgVec<T> w, BicgCtrl* ctrl,
+                                                      double* part) {
+  __shared__ double sh[VBLOCK / 64], bc[2];
+  if (ctrl->status) return;
+  const int64_t stride = (int64_t)gridDim.x * VBLOCK;
+  const int64_t i0 = (int64_t)blockIdx.x * VBLOCK + threadIdx.x;
+  double a0 = 0, a1 = 0;
+  if (stage == BICG_DIR) {
+    if (ctrl->finish) {  // the last update met the tolerance (its workgroups all completed x)
+      if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->status = CG_CONVERGED;
+      return;
+    }
+    const double rho = bicg_sum(part, 0, sh, bc);
+    const double rr = bicg_sum(part, 1, sh, bc + 1);
+    const bool first = ctrl->iters == 0 && ctrl->rho_old == 0.0;
+    const double tol2 = first ? ctrl->rtol2 * rr : ctrl->tol2;
+    int st = CG_RUNNING;
+    if (!finite(rho) || !finite(rr)) st = FE_ERR_NONFINITE;
+    else if (first ? rr == 0.0 : rr <= tol2) st = CG_CONVERGED;
+    else if (ctrl->iters >= ctrl->max_it) st = FE_ERR_NOT_CONVERGED;
+    else if (rho == 0.0 || (!first && ctrl->omega == 0.0)) st = FE_ERR_BREAKDOWN;
+    const double beta = first ? 0.0 : (rho / ctrl->rho_old) * (ctrl->alpha / ctrl->omega);
+    const double omega = first ? 0.0 : ctrl->omega;
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (first) {
+        ctrl->bb = rr;
+        ctrl->tol2 = tol2;
+      }
+      ctrl->rr = rr;
+      ctrl->rho = rho;
+      ctrl->beta = beta;
+      if (st != CG_RUNNING) ctrl->status = st;
+    }
+    if (st != CG_RUNNING) return;
+    const T tb = T(beta), to = T(omega);
+    for (int64_t nd = i0; nd < n / 3; nd += stride) {  // one node per thread: M^-1 may couple its dofs
+      T pv[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int64_t i = 3 * nd + c;
+        pv[c] = w.r[i] + tb * (w.p[i] - to * w.v[i]);
+        w.p[i] = pv[c];
+        w.v[i] = 0;
+      }
+      bicg_precond(w, nd, pv, w.ph);
+    }
+  } else if (stage == BICG_HALF) {
+    const double rv = bicg_sum(part, 2, sh, bc);
+    const double rho = ctrl->rho;
+    const int st = !finite(rv) ? FE_ERR_NONFINITE : (rv == 0.0 ? FE_ERR_BREAKDOWN : CG_RUNNING);
+    const double alpha = rho / rv;
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ctrl->alpha = alpha;
+      if (st != CG_RUNNING) ctrl->status = st;
+    }
+    if (st != CG_RUNNING) return;
+    const T ta = T(alpha);
+    for (int64_t nd = i0; nd < n / 3; nd += stride) {
+      T sv[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int64_t i = 3 * nd + c;
+        sv[c] = w.r[i] - ta * w.v[i];
+        w.sv[i] = sv[c];
+        a0 += (double)sv[c] * (double)sv[c];
+      }
+      bicg_precond(w, nd, sv, w.sh);
+    }
+  } else if (stage == BICG_DOTS) {
+    for (int64_t i = i0; i < n; i += stride) {
+      a0 += (double)w.t[i] * (double)w.sv[i];
+      a1 += (double)w.t[i] * (double)w.t[i];
+    }
+  } else {  // BICG_UPDATE
+    const double ss = bicg_sum(part, 3, sh, bc);
+    const double ts = bicg_sum(part, 4, sh, bc + 1);
+    const double tt = bicg_sum(part, 5, sh, bc);
+    const double alpha = ctrl->alpha;
+    const bool done = ss <= ctrl->tol2;
+    const double omega = done ? 0.0 : (tt > 0.0 ? ts / tt : 0.0);
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ctrl->omega = omega;
+      ctrl->rho_old = ctrl->rho;
+      ctrl->iters += 1;
+      if (done) {  // not the status word: the other workgroups of this launch still update x
+        ctrl->rr = ss;
+        ctrl->finish = 1;
+      }
+    }
+    const T ta = T(alpha), to = T(omega);
+    for (int64_t i = i0; i < n; i += stride) {
+      if (done) {
+        w.x[i] += ta * w.ph[i];
+        continue;
+      }
+      w.x[i] += ta * w.ph[i] + to * w.sh[i];
+      const T ri = w.sv[i] - to * w.t[i];
+      w.r[i] = ri;
+      w.t[i] = 0;
+      a0 += (double)w.rh[i] * (double)ri;
+      a1 += (double)ri * (double)ri;
+    }
+  }
+  const int s0 = stage == BICG_HALF ? 3 : (stage == BICG_DOTS ? 4 : 0);
+  if (stage != BICG_DIR) {
+    a0 = block_sum(a0, sh);
+    a1 = block_sum(a1, sh);
+    if (threadIdx.x == 0) {
+      part[(int64_t)s0 * BICG_GRID + blockIdx.x] = a0;
+      if (stage != BICG_HALF) part[(int64_t)(s0 + 1) * BICG_GRID + blockIdx.x] = a1;
+    }
+  }
+}
+
+// (r_hat, v) partials after the operator
+template <typename T>
+__global__ __launch_bounds__(VBLOCK) void bicg_rv_kernel(int64_t n, const T* rh, const T* v, BicgCtrl* ctrl,
+                                                         double* part) {
+  __shared__ double sh[VBLOCK / 64];
+  if (ctrl->status) return;
+  double a = 0;
+  for (int64_t i = (int64_t)blockIdx.x * VBLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * VBLOCK)
+    a += (double)rh[i] * (double)v[i];
+  a = block_sum(a, sh);
+  if (threadIdx.x == 0) part[2 * BICG_GRID + blockIdx.x] = a;
+}
+
+// x = 0, r = r_hat = b, p = v = t = 0; partials (r_hat, r) = ||b||^2 and ||r||^2
+template <typename T>
+__global__ __launch_bounds__(VBLOCK) void bicg_init_kernel(int64_t n, const T* b, BicgVec<T> w, BicgCtrl* ctrl,
+                                                           double* part, double rtol, int max_it, int invert) {
+  __shared__ double sh[VBLOCK / 64];
+  double bb = 0;
+  for (int64_t i = (int64_t)blockIdx.x * VBLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * VBLOCK) {
+    const T bi = b[i];
+    w.x[i] = 0;
+    w.r[i] = bi;
+    w.rh[i] = bi;
+    w.p[i] = 0;
+    w.v[i] = 0;
+    w.t[i] = 0;
+    if (invert) const_cast<T*>(w.M)[i] = T(1) / w.M[i];
+    bb += (double)bi * (double)bi;
+  }
+  bb = block_sum(bb, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = bb;
+    part[BICG_GRID + blockIdx.x] = bb;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl->rho = ctrl->rho_old = ctrl->alpha = ctrl->omega = ctrl->beta = 0;
+    ctrl->rtol2 = rtol * rtol;
+    ctrl->iters = 0;
+    ctrl->max_it = max_it;
+    ctrl->status = CG_RUNNING;
+    ctrl->finish = 0;
+  }
+}
+
+template <typename T> static BicgVec<T> bicg_vec(const fe_problem* p, void* x) {
+  BicgVec<T> w;
+  T* base = static_cast<T*>(p->w_bicg);
+  const int64_t n = p->n_dof;
+  w.x = static_cast<T*>(x);
+  w.r = base;
+  w.rh = base + n;
+  w.p = base + 2 * n;
+  w.v = base + 3 * n;
+  w.sv = base + 4 * n;
+  w.t = base + 5 * n;
+  w.ph = base + 6 * n;
+  w.sh = base + 7 * n;
+  w.M = static_cast<const T*>(pc_buffer(p));
+  w.block = p->precond == FE_PC_BLOCK_JACOBI;
+  return w;
+}
+
+template <typename T>
+static hipError_t bicg_init_t(const fe_problem* p, const T* b, void* x, double rtol, int max_it, hipStream_t s) {
+  hipLaunchKernelGGL(bicg_init_kernel<T>, dim3(BICG_GRID), dim3(VBLOCK), 0, s, p->n_dof, b, bicg_vec<T>(p, x),
+                     p->bicg_ctrl, p->bicg_part, rtol, max_it, p->precond == FE_PC_BLOCK_JACOBI ? 0 : 1);
+  return hipGetLastError();
+}
+
+hipError_t bicg_init(const fe_problem* p, const void* b, void* x, double rtol, int max_it, hipStream_t s) {
+  return p->prec == FE_F64 ? bicg_init_t(p, (const double*)b, x, rtol, max_it, s)
+                           : bicg_init_t(p, (const float*)b, x, rtol, max_it, s);
+}
+
+template <typename T> static hipError_t bicg_step_t(const fe_problem* p, int stage, void* x, hipStream_t s) {
+  const BicgVec<T> w = bicg_vec<T>(p, x);
+  if (stage == 4) {  // (r_hat, v) after the first operator
+    hipLaunchKernelGGL(bicg_rv_kernel<T>, dim3(BICG_GRID), dim3(VBLOCK), 0, s, p->n_dof, (const T*)w.rh,
+                       (const T*)w.v, p->bicg_ctrl, p->bicg_part);
+  } else {
+    hipLaunchKernelGGL(bicg_kernel<T>, dim3(BICG_GRID), dim3(VBLOCK), 0, s, stage, p->n_dof, w, p->bicg_ctrl,
+                       p->bicg_part);
+  }
+  return hipGetLastError();
+}
+
+hipError_t bicg_step(const fe_problem* p, int stage, void* x, hipStream_t s) {
+  return p->prec == FE_F64 ? bicg_step_t<double>(p, stage, x, s) : bicg_step_t<float>(p, stage, x, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,114 @@
+"""Device BiCGStab against the oracle's BiCGStab and dense solves: the SPD
+config-1 operator (matrix-free and CSR) and a nonsymmetric CSR matrix on the same
+pattern; then a surrogate-driven Newton ramp with the network Jacobian itself as
+tangent (nonsymmetric operator) solved by BiCGStab."""
+import numpy as np
+import pytest
+
+from helpers import PHASES_CONFIG1, lib_materials, oracle_phases, rel_err
+from oracle import assembly, solver
+from oracle.rve import RVE
+from paper_2604_22087_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _config1(prec="f64"):
+    import torch
+    from paper_2604_22087_amd import fe
+    n = 8
+    phase = inputs.sphere_phase(n)
+    rve = RVE(n, phase, oracle_phases(PHASES_CONFIG1))
+    P = fe.Problem(n, prec)
+    models, params = lib_materials(PHASES_CONFIG1)
+    P.set_materials(torch.tensor(phase, device="cuda"), models, params)
+    P.set_dirichlet(torch.tensor(inputs.boundary_dof_mask(n), device="cuda"))
+    return n, rve, P
+
+
+@pytest.mark.parametrize("op", ["matfree", "csr"])
+def test_bicgstab_spd_config1(op):
+    import torch
+    from paper_2604_22087_amd import fe
+    print(f"[bicgstab spd] op={op}", flush=True)
+    n, rve, P = _config1()
+    eb = np.diag([0.01, 0.0, 0.0])
+    u0 = rve.affine_lift(eb)
+    r_e, k_e, _ = rve.element_residual_tangent(u0)
+    rhs = -assembly.assemble_vector(rve.conn, r_e, rve.n_dof) * rve.free
+    d = solver.matfree_diagonal(rve.conn, k_e, rve.n_dof, rve.mask)
+    x_ref, it_ref, st, _ = solver.bicgstab(lambda x: solver.matfree_apply(rve.conn, k_e, x, rve.mask), rhs, 1e-12,
+                                           2000, precond=lambda r: r / d)
+    assert st == solver.OK
+    u = P.vector()
+    P.lift(eb, u, zero_free=True)
+    b = P.residual(u, apply_bc=True, store_tangent=True)
+    b.neg_()
+    csr = None
+    if op == "csr":
+        rp, ci = P.csr_indices()
+        csr = (rp, ci, P.tangent_csr(u, apply_bc=True))
+    x, res = P.pcg(b, op=fe.OP_CSR if csr else fe.OP_MATFREE, csr=csr, rtol=1e-12, max_it=2000,
+                   solver=fe.SOLVER_BICGSTAB)
+    print(f"  iterations {res.iterations} (oracle {it_ref})", flush=True)
+    assert res.status == 0
+    assert abs(res.iterations - it_ref) <= 3
+    assert rel_err(x.cpu().numpy(), x_ref) <= 1e-9
+
+
+def test_bicgstab_nonsymmetric_csr():
+    import torch
+    from paper_2604_22087_amd import fe
+    n, rve, P = _config1()
+    u0 = rve.affine_lift(np.diag([0.01, 0.0, 0.0]))
+    _, k_e, _ = rve.element_residual_tangent(u0)
+    rp, ci, v = rve.bc_csr(k_e)
+    rows = assembly.csr_rows(rp)
+    rng = np.random.default_rng(12)
+    free = (rve.mask[rows] == 0) & (rve.mask[ci] == 0) & (rows != ci)
+    v = v.copy()
+    v[free] += 0.05 * np.abs(v[free]) * rng.uniform(-1, 1, free.sum())   # nonsymmetric perturbation
+    b = rng.normal(size=rve.n_dof) * rve.free
+    d = assembly.csr_diagonal(rp, ci, v)
+    x_ref, it_ref, st, _ = solver.bicgstab(lambda x: assembly.csr_matvec(rp, ci, v, x), b, 1e-12, 4000,
+                                           precond=lambda r: r / d)
+    assert st == solver.OK
+    dense = np.zeros((rve.n_dof, rve.n_dof))
+    dense[rows, ci] = v
+    assert np.abs(dense - dense.T).max() > 1e-3 * np.abs(dense).max()
+    csr = (torch.tensor(rp, dtype=torch.int32, device="cuda"), torch.tensor(ci, dtype=torch.int32, device="cuda"),
+           torch.tensor(v, device="cuda"))
+    x, res = P.pcg(torch.tensor(b, device="cuda"), op=fe.OP_CSR, csr=csr, rtol=1e-12, max_it=4000,
+                   solver=fe.SOLVER_BICGSTAB)
+    print(f"  nonsymmetric: iterations {res.iterations} (oracle {it_ref})", flush=True)
+    assert res.status == 0
+    assert abs(res.iterations - it_ref) <= 5
+    x_dense = np.linalg.solve(dense, b)
+    assert rel_err(x.cpu().numpy(), x_dense) <= 1e-9
+
+
+def test_surrogate_full_jacobian_with_bicgstab():
+    import torch
+    from paper_2604_22087_amd import fe
+    from paper_2604_22087_amd import surrogate as S
+    W = S.load_weights()
+    if W is None:
+        pytest.skip("no trained surrogate parameters in the package")
+    n = 16
+    path = S.ramp(0.02, 5)
+    ref = S.fiber_problem(n)
+    _, _, s_rm, _ = ref.newton(path, state=ref.state(), op=fe.OP_MATFREE, newton_rtol=1e-6, pcg_rtol=1e-8,
+                               max_newton=30)
+    out = {}
+    for full, solv in ((False, fe.SOLVER_CG), (True, fe.SOLVER_BICGSTAB)):
+        P = S.fiber_problem(n)
+        P.set_surrogate(W, fallback_tol=1e-3)
+        P.set_surrogate_tangent(full)
+        _, _, sig, info = P.newton(path, state=P.state(), op=fe.OP_MATFREE, newton_rtol=1e-6, pcg_rtol=1e-8,
+                                   max_newton=30, solver=solv)
+        out[full] = (np.array(sig), info, P.surrogate_stats())
+        print(f"  full={full}: {info} {out[full][2]}", flush=True)
+        assert info["steps_done"] == len(path)
+        err = np.max(np.abs(np.array(sig)[:, 0] - np.array(s_rm)[:, 0]) / np.abs(np.array(s_rm)[:, 0]))
+        assert err <= 1e-3
+    assert out[True][2]["accepted"] > 0
