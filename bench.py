@@ -81,20 +81,23 @@ def run_ramp(P, u, state, path):
 
 def operator_rates(P, u, state, reps=50):
     """K*u rates at the current linearisation: matrix-free and assembled CSR, each hot (back to back,
-    as inside PCG) and cold (a 1 GiB write before every launch evicts the 256 MB last-level cache).
+    as inside PCG) and cold (a 1 GiB read before every launch evicts the 256 MB last-level cache
+    without leaving dirty lines behind).
     Times are the library's own HIP events around each launch; bytes are algorithmic."""
     import torch
     from paper_2604_22087_amd import fe
     g = torch.Generator(device="cuda").manual_seed(0)
     x = torch.randn(P.n_dof, dtype=P.dtype, device="cuda", generator=g)
     y = P.vector()
-    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    flush = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    sink = torch.empty(1, dtype=torch.float64, device="cuda")
     rp, ci = P.csr_indices()
     vals = P.tangent_csr(u, state, apply_bc=True)
     P.residual(u, state, P.state(), apply_bc=True, store_tangent=True)  # matrix-free linearisation = CSR's
     out = {}
     calls = (("matfree", "matfree_apply", lambda: P.apply_matfree(x, y, apply_bc=True)),
-             ("csr", "csr_spmv", lambda: P.apply_csr(rp, ci, vals, x, y)))
+             ("csr", "csr_spmv", lambda: P.apply_csr(rp, ci, vals, x, y)),
+             ("csr_nodal", "csr_spmv_nodal", lambda: P.apply_csr_nodal(rp, ci, vals, x, y)))
     for name, key, call in calls:
         for mode in ("hot", "cold"):
             for _ in range(5):
@@ -103,7 +106,7 @@ def operator_rates(P, u, state, reps=50):
             P.profile(True)
             for k in range(reps):
                 if mode == "cold":
-                    flush.fill_(float(k))
+                    torch.sum(flush, dim=0, keepdim=True, out=sink)
                 call()
             c, ms, by = P.profile_read()[key]
             P.profile(False)

@@ -153,6 +153,14 @@ int fe_apply_matfree(fe_problem* p, const void* x, void* y, int apply_bc, void* 
 int fe_apply_csr(fe_problem* p, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
                  const void* x, void* y, void* stream);
 
+/* CSR y = A x for a matrix in the node-structured pattern of fe_csr_indices
+ * (rows 3a, 3a+1, 3a+2 have identical column lists): the column indices and the
+ * gathered x of a node's first row serve all three rows, so index traffic is a
+ * third of fe_apply_csr's.  Results equal fe_apply_csr's (same products and sums,
+ * possibly in another order).  The pattern is not checked. */
+int fe_apply_csr_nodal(fe_problem* p, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
+                       const void* x, void* y, void* stream);
+
 /* Diagonal of the (masked, if apply_bc) matrix-free operator: d real [n_dof]. */
 int fe_diagonal(fe_problem* p, void* d, int apply_bc, void* stream);
 
@@ -226,17 +234,18 @@ int fe_mean_stress(fe_problem* p, const void* u, const void* state_in, double* s
                    void* stream);
 
 /* Kernel timing for measurement.  While enabled, the library records a HIP
- * event pair on the call's stream around each launch of: class 0 the
- * matrix-free operator kernel (fe_apply_matfree and inside CG), class 1 the CSR
- * mat-vec (fe_apply_csr and inside CG), class 2 the residual / return-map
- * element kernel, class 3 the CSR tangent kernel.  enable = 1 clears previous
- * records; enable = 0 stops recording.  fe_profile_read synchronises the
- * device and writes, for c = 0..3, out_host[3*c] = launches, out_host[3*c+1] =
- * summed milliseconds, out_host[3*c+2] = summed algorithmic bytes of those
- * launches for classes 0 and 1 (compulsory traffic: x read and y written once,
- * phase ids, the stored tangent values the kernel must read at the current
- * linearisation; CSR: values, column indices, row pointers, x and y once),
- * 0 for classes 2 and 3; then clears the records. */
+ * event pair inside the dispatch of each launch of: class 0 the matrix-free
+ * operator kernel (fe_apply_matfree and inside CG), class 1 the CSR mat-vec
+ * (fe_apply_csr and inside CG), class 2 the residual / return-map element
+ * kernel, class 3 the CSR tangent kernel, class 4 the node-structured CSR
+ * mat-vec (fe_apply_csr_nodal).  enable = 1 clears previous records; enable = 0
+ * stops recording.  fe_profile_read synchronises the device and writes, for
+ * c = 0..4, out_host[3*c] = launches, out_host[3*c+1] = summed milliseconds,
+ * out_host[3*c+2] = summed algorithmic bytes of those launches for classes 0, 1
+ * and 4 (compulsory traffic: x read and y written once, phase ids, the stored
+ * tangent values the kernel must read at the current linearisation; CSR:
+ * values, column indices (one list per node for class 4), row pointers, x and
+ * y once), 0 for classes 2 and 3; then clears the records.  out_host: 15 doubles. */
 int fe_profile(fe_problem* p, int enable);
 int fe_profile_read(fe_problem* p, double* out_host);
 

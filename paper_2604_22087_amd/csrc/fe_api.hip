@@ -476,6 +476,18 @@ int fe_apply_csr(fe_problem* p, const int32_t* row_ptr, const int32_t* col_idx, 
   return FE_OK;
 }
 
+int fe_apply_csr_nodal(fe_problem* p, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
+                       const void* x, void* y, void* stream) {
+  CHKP(p);
+  if (!row_ptr || !col_idx || !vals || !x || !y) return arg_error("all CSR arrays and vectors are required");
+  PROF(p, S(stream), 4, launch_spmv_nodal(p, row_ptr, col_idx, vals, x, y, S(stream)));
+  if (p->prof) {  // one column list per node triple
+    const double w = (double)real_size(p);
+    p->prof_bytes[4] += (w + 4.0 / 3.0) * (double)p->nnz + 4.0 * (double)(p->n_dof + 1) + 2.0 * w * (double)p->n_dof;
+  }
+  return FE_OK;
+}
+
 int fe_diagonal(fe_problem* p, void* d, int apply_bc, void* stream) {
   CHKP(p);
   if (!d) return arg_error("d is required");
@@ -825,7 +837,7 @@ extern "C" int fe_profile(fe_problem* p, int enable) {
 extern "C" int fe_profile_read(fe_problem* p, double* out) {
   CHKP(p);
   if (!out) return arg_error("out is null");
-  for (int k = 0; k < 12; ++k) out[k] = 0;
+  for (int k = 0; k < 15; ++k) out[k] = 0;
   HIPCHK(hipDeviceSynchronize());
   for (const auto& r : p->prof_recs) {
     float ms = 0;
@@ -833,7 +845,7 @@ extern "C" int fe_profile_read(fe_problem* p, double* out) {
     out[3 * r.first] += 1;
     out[3 * r.first + 1] += ms;
   }
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < 5; ++c) {
     out[3 * c + 2] = p->prof_bytes[c];
     p->prof_bytes[c] = 0;
   }

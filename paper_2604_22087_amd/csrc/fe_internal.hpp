@@ -183,7 +183,7 @@ struct fe_problem {
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, size_t>> prof_recs;  // (kernel class, index of the start event)
   size_t ev_used = 0;
-  double prof_bytes[4] = {0, 0, 0, 0};            // algorithmic bytes of the recorded launches
+  double prof_bytes[5] = {0, 0, 0, 0, 0};         // algorithmic bytes of the recorded launches
 };
 
 namespace fe {
@@ -220,6 +220,8 @@ hipError_t launch_tangent_csr(const fe_problem* p, void* vals, int apply_bc, hip
 hipError_t launch_spmv(const fe_problem* p, const int32_t* rp, const int32_t* ci, const void* v,
                        const void* x, void* y, hipStream_t s);
 hipError_t launch_fill(const fe_problem* p, void* x, int64_t n, double v, hipStream_t s);
+hipError_t launch_spmv_nodal(const fe_problem* p, const int32_t* rp, const int32_t* ci, const void* v, const void* x,
+                             void* y, hipStream_t s);
 hipError_t launch_lift(const fe_problem* p, const double* eps, void* u, int zero_free, hipStream_t s);
 hipError_t launch_axpby(const fe_problem* p, int64_t n, double a, const void* x, double b, void* y,
                         hipStream_t s);

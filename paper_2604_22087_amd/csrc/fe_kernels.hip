@@ -1325,6 +1325,55 @@ __global__ __launch_bounds__(256) void spmv_kernel(int64_t n_rows, const int32_t
 
 constexpr int SPMV_LPR = 16;
 
+// Node-structured CSR (the pattern of the structured mesh): rows 3a, 3a+1, 3a+2 share one
+// column list, so the column indices and the gathered x of the first row serve all three.
+// LPN lanes per node; y = A x.
+template <typename T, int LPN>
+__global__ __launch_bounds__(256) void spmv_nodal_kernel(int64_t n_nodes, const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ ci, const T* __restrict__ v,
+                                                         const T* __restrict__ x, T* __restrict__ y,
+                                                         const int* stop) {
+  if (stop && *stop) return;
+  const int64_t nd = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPN;
+  const int lane = threadIdx.x % LPN;
+  T a0 = 0, a1 = 0, a2 = 0;
+  if (nd < n_nodes) {
+    const int b0 = rp[3 * nd], b1 = rp[3 * nd + 1], b2 = rp[3 * nd + 2];
+    const int len = b1 - b0;
+    for (int k = lane; k < len; k += LPN) {
+      const T xv = x[ci[b0 + k]];
+      a0 += v[b0 + k] * xv;
+      a1 += v[b1 + k] * xv;
+      a2 += v[b2 + k] * xv;
+    }
+  }
+#pragma unroll
+  for (int off = LPN / 2; off > 0; off >>= 1) {
+    a0 += __shfl_xor(a0, off, LPN);
+    a1 += __shfl_xor(a1, off, LPN);
+    a2 += __shfl_xor(a2, off, LPN);
+  }
+  if (nd < n_nodes && lane < 3) y[3 * nd + lane] = lane == 0 ? a0 : (lane == 1 ? a1 : a2);
+}
+
+constexpr int SPMV_LPN = 32;
+
+template <typename T>
+static hipError_t launch_spmv_nodal_t(const fe_problem* p, const int32_t* rp, const int32_t* ci, const T* v,
+                                      const T* x, T* y, const int* stop, hipStream_t s) {
+  const int64_t threads = p->n_nodes * SPMV_LPN;
+  timed_launch((spmv_nodal_kernel<T, SPMV_LPN>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+               p->n_nodes, rp, ci, v, x, y, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv_nodal(const fe_problem* p, const int32_t* rp, const int32_t* ci, const void* v, const void* x,
+                             void* y, hipStream_t s) {
+  return p->prec == FE_F64
+             ? launch_spmv_nodal_t(p, rp, ci, (const double*)v, (const double*)x, (double*)y, nullptr, s)
+             : launch_spmv_nodal_t(p, rp, ci, (const float*)v, (const float*)x, (float*)y, nullptr, s);
+}
+
 template <typename T>
 static hipError_t launch_spmv_t(const fe_problem* p, const int32_t* rp, const int32_t* ci, const T* v, const T* x,
                                 T* y, const int* stop, hipStream_t s) {

@@ -61,6 +61,7 @@ SIGNATURES = [
     ("fe_apply_csr", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("fe_diagonal", _i32, [_vp, _vp, _i32, _vp]),
     ("fe_set_preconditioner", _i32, [_vp, _i32]),
+    ("fe_apply_csr_nodal", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("fe_set_surrogate_tangent", _i32, [_vp, _i32]),
     ("fe_vjp_path", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("fe_pcg", _i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _dbl, _i32, ctypes.POINTER(PcgInfo), _vp]),
@@ -239,6 +240,14 @@ class Problem:
                                      _stream()), "fe_apply_csr")
         return y
 
+    def apply_csr_nodal(self, row_ptr, col_idx, vals, x, y=None):
+        """y = A x for a matrix in the node-structured pattern of csr_indices()."""
+        self._real(x, self.n_dof, "x")
+        y = self.vector() if y is None else self._real(y, self.n_dof, "y")
+        _check(self.lib.fe_apply_csr_nodal(self.handle, _ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(x), _ptr(y),
+                                           _stream()), "fe_apply_csr_nodal")
+        return y
+
     def diagonal(self, apply_bc=False, d=None):
         d = self.vector() if d is None else self._real(d, self.n_dof, "d")
         _check(self.lib.fe_diagonal(self.handle, _ptr(d), int(apply_bc), _stream()), "fe_diagonal")
@@ -314,14 +323,14 @@ class Problem:
         return f.value
 
     # -- measurement -------------------------------------------------------------------
-    KERNEL_CLASSES = ("matfree_apply", "csr_spmv", "residual", "tangent_csr")
+    KERNEL_CLASSES = ("matfree_apply", "csr_spmv", "residual", "tangent_csr", "csr_spmv_nodal")
 
     def profile(self, enable=True):
         _check(self.lib.fe_profile(self.handle, int(enable)), "fe_profile")
 
     def profile_read(self):
         """{class: (launches, total_ms, algorithmic_bytes)} since profiling was enabled (synchronises)."""
-        out = (_dbl * 12)()
+        out = (_dbl * 15)()
         _check(self.lib.fe_profile_read(self.handle, out), "fe_profile_read")
         return {k: (int(out[3 * i]), float(out[3 * i + 1]), float(out[3 * i + 2]))
                 for i, k in enumerate(self.KERNEL_CLASSES)}
