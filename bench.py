@@ -245,6 +245,25 @@ def adjoint_path_leg(n):
             "checkpoint_bytes": 3 * (56 * P.n_el + P.n_dof) * 8}
 
 
+def csr_scaling_leg(sizes):
+    """Assembled-operator K*u at larger meshes: the fiber RVE's CSR tangent at an affine strain
+    eps_xx = 0.004 (elastic linearisation), node-structured and general CSR mat-vec, FP64 and FP32,
+    hot and cold (1 GiB read between launches)."""
+    import torch
+    out = {}
+    for n in sizes:
+        for prec in ("f64", "f32"):
+            P, _ = setup(n, prec)
+            u = P.vector()
+            P.lift(np.diag([0.004, 0.0, 0.0]), u)
+            r = operator_rates(P, u, P.state(), reps=20)
+            out[f"{n}^3_{prec}"] = {k: {"us": v["us"], "gdofs": v["gdofs"], "frac": v["frac"]}
+                                    for k, v in r.items() if k.startswith("csr")}
+            del P, u, r
+            torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(n, phase, gpu_info, path):
     """The FP64 oracle on a bounded sample of the same workload (host cores)."""
     from oracle import solver
@@ -286,6 +305,7 @@ def main():
     ap.add_argument("--nh", type=int, default=0, help="also run the finite-strain Neo-Hookean leg at this n (0: skip)")
     ap.add_argument("--surrogate", type=int, default=96, help="n of the surrogate-vs-return-map leg (0: skip)")
     ap.add_argument("--adjoint-path", type=int, default=64, help="n of the plastic-path adjoint leg (0: skip)")
+    ap.add_argument("--csr-sizes", default="96,128", help="mesh sizes of the assembled-operator leg ('' to skip)")
     ap.add_argument("--copy-calib", action="store_true", help="run only a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -379,6 +399,10 @@ def main():
     if args.surrogate:
         print(f"[bench] surrogate leg {args.surrogate}^3", file=sys.stderr, flush=True)
         out["surrogate"] = surrogate_leg(args.surrogate)
+    if args.csr_sizes:
+        sizes = [int(v) for v in args.csr_sizes.split(",") if v]
+        print(f"[bench] assembled-operator leg {sizes}", file=sys.stderr, flush=True)
+        out["csr_scaling"] = csr_scaling_leg(sizes)
     if args.adjoint_path:
         print(f"[bench] adjoint path leg {args.adjoint_path}^3", file=sys.stderr, flush=True)
         out["adjoint_path"] = adjoint_path_leg(args.adjoint_path)
