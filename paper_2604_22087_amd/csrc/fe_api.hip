@@ -135,6 +135,7 @@ void fe_problem_destroy(fe_problem* p) {
   free_dev(p->w_d);
   free_dev(p->w_blk);
   free_dev(p->w_bicg);
+  free_dev(p->w_cg);
   free_dev(p->bicg_part);
   free_dev(p->bicg_ctrl);
   free_dev(p->w_v);
@@ -180,7 +181,8 @@ int fe_problem_create(fe_problem** out, int n, int precision) {
   const size_t rs = real_size(p), vec = rs * p->n_dof;
   int st = FE_OK;
   const size_t n_part =
-      std::max<size_t>(2 * 1024, (size_t)std::max<int64_t>(elem_grid_size(n), SPMV_MAXGRID) + 2 * CG_UGRID);
+      std::max<size_t>({(size_t)2 * 1024, (size_t)std::max<int64_t>(elem_grid_size(n), SPMV_MAXGRID) + 2 * CG_UGRID,
+                        (size_t)9 * CGS_SLOTS});
   if ((st = alloc((void**)&p->phase, p->n_el)) || (st = alloc(&p->w_r, vec)) || (st = alloc(&p->w_p, vec)) ||
       (st = alloc(&p->w_p2, vec)) || (st = alloc(&p->w_q, vec)) || (st = alloc(&p->w_d, vec)) ||
       (st = alloc((void**)&p->partials, n_part * sizeof(double))) ||
@@ -531,13 +533,24 @@ static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, 
   } else {
     HIPCHK(launch_diag(p, p->w_d, 1, s));
   }
-  HIPCHK(cg_init(p, b, x, rtol, max_it, s));
+  const bool fused = op == FE_OP_MATFREE;
+  if (fused) {
+    if (!p->w_cg && alloc(&p->w_cg, 6 * real_size(p) * (size_t)p->n_dof)) return FE_ERR_OOM;
+    HIPCHK(cgs_init(p, b, x, rtol, max_it, s));
+  } else {
+    HIPCHK(cg_init(p, b, x, rtol, max_it, s));
+  }
   const size_t rec0 = p->prof_recs.size();
   const int cls = op == FE_OP_CSR ? 1 : 0;
   int launched = 0, chunk = 8;
   long k = 0;
+  if (fused) PROF(p, s, cls, cgs_operator(p, x, 0, s));
   for (;;) {
     for (int c = 0; c < chunk; ++c, ++k) {
+      if (fused) {
+        PROF(p, s, cls, cgs_operator(p, x, k + 1, s));
+        continue;
+      }
       HIPCHK(cg_pre(p, op, k, s));
       PROF(p, s, cls, cg_operator(p, op, rp, ci, vals, k, s));
       HIPCHK(cg_vectors(p, op, x, k, s));
@@ -551,15 +564,16 @@ static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, 
   const CgCtrl& c = *p->host_ctrl;
   const int status = c.status == CG_RUNNING ? FE_ERR_NOT_CONVERGED : (c.status == CG_CONVERGED ? FE_OK : c.status);
   // operator launches after the stopping iteration returned at once: drop their timings
-  const size_t executed = (size_t)c.iters + (status == FE_ERR_BREAKDOWN || status == FE_ERR_NONFINITE ? 1 : 0);
+  // (the fused form runs one launch more than iterations: launch j forms u_j = M^-1 r_j)
+  const size_t executed = (size_t)c.iters + (fused ? 1 : 0) +
+                          (!fused && (status == FE_ERR_BREAKDOWN || status == FE_ERR_NONFINITE) ? 1 : 0);
   if (p->prof) {
     if (p->prof_recs.size() > rec0 + executed) p->prof_recs.resize(rec0 + executed);
     double b = 0;
     if (int e = operator_bytes(p, op, s, &b)) return e;
-    // the fused matrix-free CG operator reads r, M^-1 (1 or 2 reals per dof), p_old and
-    // writes p instead of reading x
-    if (op == FE_OP_MATFREE)
-      b += (p->precond == FE_PC_BLOCK_JACOBI ? 4.0 : 3.0) * (double)real_size(p) * (double)p->n_dof;
+    // the fused matrix-free CG launch reads r, w, s, p, x and M^-1 (1 or 2 reals per dof)
+    // and writes r, s, p, x and the zeroed w instead of reading x
+    if (fused) b += (p->precond == FE_PC_BLOCK_JACOBI ? 11.0 : 10.0) * (double)real_size(p) * (double)p->n_dof;
     p->prof_bytes[cls] += b * (double)executed;
   }
   if (info) {
@@ -568,7 +582,7 @@ static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, 
     info->bnorm = std::sqrt(c.bb);
     info->relres = c.bb > 0 ? std::sqrt(c.rr / c.bb) : 0.0;
   }
-  if (applies) *applies += c.iters + (status == FE_ERR_BREAKDOWN || status == FE_ERR_NONFINITE ? 1 : 0);
+  if (applies) *applies += (int)executed;
   if (status != FE_OK) set_error(fe_status_string(status));
   return status;
 }

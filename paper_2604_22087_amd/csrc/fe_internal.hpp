@@ -39,7 +39,7 @@ enum ElemOp {
   OP_RESID = 0,   // r = sum_e A_e^T r_e(u)        (+ state / linearisation side outputs)
   OP_APPLY = 1,   // y = K_lin x                   (matrix-free)
   OP_VJP = 2,     // out_e = lambda_e . d r_e / d s_e
-  OP_CG_APPLY = 3 // CG: p = M^-1 r + beta p_old (written by the owning brick), q = A p, p.Ap -> alpha
+  OP_CG_APPLY = 3 // single-reduction CG launch: vector updates, u = M^-1 r, w = A u, three dot partials
 };
 
 // CG status word: kernels stop on any non-zero value, so "converged" must differ from 0.
@@ -49,6 +49,9 @@ constexpr int CG_UGRID = 512;        // workgroups of the CG vector kernels (= u
 constexpr int SPMV_MAXGRID = 2048;   // workgroups of the CG mat-vec (grid-stride over rows)
 
 // Device scalar block used by CG (one per problem).
+// single-reduction CG: slots per reduced quantity that the workgroups of a launch add into
+constexpr int CGS_SLOTS = 256;
+
 struct CgCtrl {
   double rz[2];     // r.M^-1 r after update k-1, slot k&1 (written by the direction step of iteration k)
   double pq;        // p.Ap of the last operator
@@ -61,6 +64,7 @@ struct CgCtrl {
   int status;       // CG_RUNNING, CG_CONVERGED or an fe_status error code
   int max_it;
   int pad;
+  double ghist[2], ahist[2];  // single-reduction CG: (r, M^-1 r) and alpha of iterate i in slot i & 1
 };
 
 // Device scalar block of BiCGStab (one per problem).
@@ -106,16 +110,22 @@ struct ElemArgs {
   double sur_tol;
   int sur_full;           // 1: the network Jacobian as tangent (nonsymmetric), 0: its symmetric part
   unsigned int sur_stride, sur_salt;
-  // OP_CG_APPLY only
-  const void* cg_r;       // residual r
+  // OP_CG_APPLY only (single-reduction CG, one operator launch per iteration; see the kernel)
+  long cg_j;              // launch index j; launch 0 makes no update, only u_0 = M^-1 b and w_0 = A u_0
+  const void* cg_rold;    // r_{j-1}
+  void* cg_rnew;          // r_j (written by owners)
+  const void* cg_wold;    // w_{j-1} = A u_{j-1}
+  void* cg_wzero;         // the w buffer of launch j+1 (zeroed by owners)
+  const void* cg_sold;    // s_{j-2}
+  void* cg_snew;          // s_{j-1} (written by owners)
+  void* cg_pvec;          // p (updated in place by owners)
+  void* cg_x;             // x (updated in place by owners)
   const void* cg_dinv;    // preconditioner: inverse diagonal [n_dof] or inverse node blocks [n_nodes][6]
   int cg_block;           // 1: node-block Jacobi
-  const void* cg_pold;    // previous search direction
-  void* cg_pnew;          // new search direction (written)
-  CgCtrl* ctrl;
-  double* cg_pa;          // per-workgroup partials of p.Ap (written)
-  const double* cg_pu;    // partials of the previous update (r.r, r.M^-1 r)
-  long cg_k;              // iteration index
+  CgCtrl* ctrl;           // scalars and status (workgroup 0 writes those of launch j)
+  const double* cg_acc_in;// [3][CGS_SLOTS] sums of launch j-1: (u, A u), (r, u), ||r||^2
+  double* cg_acc_out;     // [3][CGS_SLOTS] sums of launch j (atomics; zeroed by launch j-1)
+  double* cg_acc_zero;    // [3][CGS_SLOTS] slots of launch j+1 (zeroed by workgroup 0)
 };
 
 template <typename T> struct Buf { T* p = nullptr; };
@@ -145,6 +155,7 @@ struct fe_problem {
   void* w_d = nullptr;        // inverse diagonal
   int precond = FE_PC_JACOBI; // FE_PC_JACOBI or FE_PC_BLOCK_JACOBI
   void* w_blk = nullptr;      // inverse node blocks [n_nodes][6] (allocated on first use)
+  void* w_cg = nullptr;       // single-reduction CG vectors r_1, s_0, s_1, w_0, w_1, w_2 (allocated on first use)
   void* w_bicg = nullptr;     // BiCGStab vectors r, r_hat, p, v, s, t, p_hat, s_hat (allocated on first use)
   double* bicg_part = nullptr;  // BiCGStab partial sums [8][BICG_GRID]
   fe::BicgCtrl* bicg_ctrl = nullptr;
@@ -253,13 +264,17 @@ hipError_t launch_path_vjp(const fe_problem* p, const void* u, const void* hist,
 hipError_t launch_mlp_forward_counted(const float* W, const float* x, float* y, float* jac, int64_t cap,
                                       const unsigned int* count, hipStream_t s);
 
-// CG pieces: one iteration = cg_operator (q = A p) then cg_vectors (scalars and updates)
+// CSR CG pieces: one iteration = cg_pre (direction), cg_operator (q = A p, p.Ap partials),
+// cg_vectors (scalars and updates)
 hipError_t cg_init(const fe_problem* p, const void* b, void* x, double rtol, int max_it, hipStream_t s);
-// (matrix-free: one fused element launch that also forms p and p.Ap, then one update launch)
 hipError_t cg_operator(const fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, long k,
                        hipStream_t s);
 hipError_t cg_vectors(const fe_problem* p, int op, void* x, long k, hipStream_t s);
 hipError_t cg_pre(const fe_problem* p, int op, long k, hipStream_t s);  // CSR: direction kernel before the mat-vec
+// matrix-free single-reduction CG: init, then one fused operator launch j = 0, 1, ... per
+// iteration (its last workgroup computes the scalars of the next launch)
+hipError_t cgs_init(const fe_problem* p, const void* b, void* x, double rtol, int max_it, hipStream_t s);
+hipError_t cgs_operator(const fe_problem* p, void* x, long j, hipStream_t s);
 int elem_grid_size(int n);  // workgroups of an element-kernel launch (also the partial-sum slots it needs)
 // partial-sum slots of a CG operator launch; the update partials (2 * CG_UGRID) follow them
 inline int64_t cg_pa_size(const fe_problem* p) { return std::max<int64_t>(elem_grid_size(p->n), SPMV_MAXGRID); }

@@ -525,6 +525,183 @@ __device__ __forceinline__ void nh_apply(const T dH[3][3], const T FiT[3][3], T 
 }
 
 // ---------------------------------------------------------------------------
+// Single-reduction CG, staging of a brick's nodes for launch j (see ElemArgs): every lane
+// first issues the loads of all its dofs, then forms
+//   s_{j-1} = w_{j-1} + beta s_{j-2},  r_j = r_{j-1} - alpha s_{j-1},  u_j = M^-1 r_j
+// (launch 0: r_0 = b, u_0 = M^-1 b).  Every brick that touches a node forms the same u_j; the
+// owner also stores s_{j-1}, r_j, p_{j-1} = u_{j-1} + beta p_{j-2}, x_j = x_{j-1} + alpha p_{j-1},
+// zeroes the w buffer of launch j+1 and adds its shares of (r_j, u_j) and ||r_j||^2.
+// u_j goes to s_x (0 on constrained dofs, whose value goes to s_b), s_y is cleared.
+constexpr int STAGE_IT = (NN * 3 + EBLOCK - 1) / EBLOCK;
+
+template <typename T, bool NEED_L>
+__device__ __forceinline__ void cg_stage_brick(const ElemArgs& a, int n, int a0, int b0, int c0, T alpha, T beta,
+                                               T* s_x, T* s_y, T* s_b, T* s_l, double& g, double& rr) {
+  const T* __restrict__ RO = static_cast<const T*>(a.cg_rold);
+  const T* __restrict__ WO = static_cast<const T*>(a.cg_wold);
+  const T* __restrict__ SO = static_cast<const T*>(a.cg_sold);
+  const T* __restrict__ M = static_cast<const T*>(a.cg_dinv);
+  const T* __restrict__ XL = static_cast<const T*>(a.xlin);
+  T* __restrict__ RN = static_cast<T*>(a.cg_rnew);
+  T* __restrict__ SN = static_cast<T*>(a.cg_snew);
+  T* __restrict__ P = static_cast<T*>(a.cg_pvec);
+  T* __restrict__ X = static_cast<T*>(a.cg_x);
+  T* __restrict__ WZ = static_cast<T*>(a.cg_wzero);
+  const unsigned char* __restrict__ mask = a.mask;
+  const bool blk = a.cg_block != 0, first = a.cg_j == 0;
+  const int64_t np1 = n + 1;
+  int64_t dofs[STAGE_IT];
+  int cs[STAGE_IT];
+  bool in[STAGE_IT], own[STAGE_IT], fixed[STAGE_IT];
+  T ro[STAGE_IT][3], wo[STAGE_IT][3], so[STAGE_IT][3], m[STAGE_IT][3], po[STAGE_IT], xo[STAGE_IT], lv[STAGE_IT];
+#pragma unroll
+  for (int t = 0; t < STAGE_IT; ++t) {
+    const int i = threadIdx.x + t * EBLOCK;
+    const int c = i % 3, nd = i / 3;
+    const int li = nd % NX, lj = (nd / NX) % NY, lk = nd / (NX * NY);
+    const int gi = a0 + li, gj = b0 + lj, gk = c0 + lk;
+    in[t] = i < NN * 3 && gi <= n && gj <= n && gk <= n;
+    own[t] = in[t] && (min(gi, n - 1) - a0 < TX) && (min(gj, n - 1) - b0 < TY) && (min(gk, n - 1) - c0 < TZ);
+    cs[t] = c;
+    const int64_t dof = in[t] ? 3 * (gi + np1 * (gj + np1 * gk)) + c : 0;
+    dofs[t] = dof;
+    const int64_t b3 = dof - c;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const bool need = in[t] && (blk || k == c);
+      ro[t][k] = need ? RO[b3 + k] : T(0);
+      wo[t][k] = need && !first ? WO[b3 + k] : T(0);
+      so[t][k] = need && !first ? SO[b3 + k] : T(0);
+    }
+    if (blk) {
+      const T* mb = M + 2 * b3;  // 6 entries per node: xx, yy, zz, yz, xz, xy
+      const int i0 = c == 0 ? 0 : (c == 1 ? 5 : 4), i1 = c == 0 ? 5 : (c == 1 ? 1 : 3),
+                i2 = c == 0 ? 4 : (c == 1 ? 3 : 2);
+      m[t][0] = in[t] ? mb[i0] : T(0);
+      m[t][1] = in[t] ? mb[i1] : T(0);
+      m[t][2] = in[t] ? mb[i2] : T(0);
+    } else {
+      m[t][0] = m[t][1] = m[t][2] = in[t] ? M[dof] : T(0);
+    }
+    fixed[t] = in[t] && mask && mask[dof];
+    po[t] = own[t] && !first ? P[dof] : T(0);
+    xo[t] = own[t] && !first ? X[dof] : T(0);
+    lv[t] = NEED_L && in[t] ? XL[dof] : T(0);
+  }
+#pragma unroll
+  for (int t = 0; t < STAGE_IT; ++t) {
+    const int i = threadIdx.x + t * EBLOCK;
+    if (i >= NN * 3) break;
+    const int c = cs[t];
+    T rn[3], sn[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      sn[k] = wo[t][k] + beta * so[t][k];
+      rn[k] = first ? ro[t][k] : ro[t][k] - alpha * sn[k];
+    }
+    T u, uo;
+    if (blk) {
+      u = m[t][0] * rn[0] + m[t][1] * rn[1] + m[t][2] * rn[2];
+      uo = m[t][0] * ro[t][0] + m[t][1] * ro[t][1] + m[t][2] * ro[t][2];
+    } else {
+      u = m[t][0] * rn[c];
+      uo = m[t][0] * ro[t][c];
+    }
+    if (own[t]) {
+      const int64_t dof = dofs[t];
+      WZ[dof] = 0;
+      if (!first) {
+        const T pn = uo + beta * po[t];
+        P[dof] = pn;
+        X[dof] = xo[t] + alpha * pn;
+        SN[dof] = sn[c];
+        RN[dof] = rn[c];
+      }
+      g += (double)rn[c] * (double)u;
+      rr += (double)rn[c] * (double)rn[c];
+    }
+    if (fixed[t]) {
+      s_b[i] = u;
+      u = 0;
+    }
+    s_x[i] = in[t] ? u : T(0);
+    s_y[i] = 0;
+    if (NEED_L) s_l[i] = lv[t];
+  }
+}
+
+// Start of single-reduction CG launch j >= 1, run redundantly by every workgroup (no
+// inter-workgroup synchronisation inside a launch): sum the slots of launch j-1 in fixed
+// order into d = (u, A u), g = (r, u), rr = ||r||^2 of iterate j-1 and form
+// (Chronopoulos & Gear 1989)
+//   beta_{j-1} = g_{j-1} / g_{j-2},  alpha_{j-1} = g_{j-1} / (d_{j-1} - beta g_{j-1} / alpha_{j-2})
+// (j = 1: beta_0 = 0, alpha_0 = g_0 / d_0), or a stop: ||r_{j-1}|| <= rtol ||b||,
+// j - 1 = max_it, breakdown, non-finite.  Workgroup 0 records the scalars and the status;
+// (g, alpha) of iterate j-1 go to history slot (j-1) & 1 while slot j & 1 is read.
+// Returns false when the iteration stops (every workgroup reaches the same decision).
+template <typename T>
+__device__ __forceinline__ bool cg_scalars(const ElemArgs& a, double (*sh)[EBLOCK / 64], T& alpha_out, T& beta_out) {
+  const long j = a.cg_j;
+  const double* acc = a.cg_acc_in;
+  double v[3] = {0, 0, 0};
+  for (int i = threadIdx.x; i < CGS_SLOTS; i += EBLOCK) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] += acc[k * CGS_SLOTS + i];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sh[k][threadIdx.x >> 6] = v[k];
+  __syncthreads();
+  double d = 0, g = 0, rr = 0;
+  for (int w = 0; w < EBLOCK / 64; ++w) {
+    d += sh[0][w];
+    g += sh[1][w];
+    rr += sh[2][w];
+  }
+  __syncthreads();  // sh is reused by the caller
+  const CgCtrl* c = a.ctrl;
+  const int slot = (int)(j & 1);  // history of iterate j-2
+  const double tol2 = j == 1 ? c->rtol2 * rr : c->tol2;
+  int st = CG_RUNNING;
+  double alpha = 0, beta = 0;
+  if (!finite(d) || !finite(g) || !finite(rr)) {
+    st = FE_ERR_NONFINITE;
+  } else if (j == 1 ? rr == 0.0 : rr <= tol2) {
+    st = CG_CONVERGED;
+  } else if (j - 1 >= c->max_it) {
+    st = FE_ERR_NOT_CONVERGED;
+  } else {
+    beta = j == 1 ? 0.0 : g / c->ghist[slot];
+    const double den = j == 1 ? d : d - beta * g / c->ahist[slot];
+    if (!finite(den)) st = FE_ERR_NONFINITE;
+    else if (den <= 0.0) st = FE_ERR_BREAKDOWN;
+    else alpha = g / den;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    CgCtrl* w = a.ctrl;
+    if (j == 1) {
+      w->bb = rr;
+      w->tol2 = tol2;
+    }
+    w->rr = rr;
+    w->pq = d;
+    w->iters = (int)(j - 1);
+    w->alpha = alpha;
+    w->beta = beta;
+    w->ghist[slot ^ 1] = g;
+    w->ahist[slot ^ 1] = alpha;
+    if (st != CG_RUNNING) w->status = st;
+  }
+  alpha_out = T(alpha);
+  beta_out = T(beta);
+  return st == CG_RUNNING;
+}
+
+// ---------------------------------------------------------------------------
 // element brick kernel
 
 // (at least two waves per SIMD: some FP64 instances sit at the 256-register edge, where
@@ -537,8 +714,8 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
   __shared__ T s_x[NN * 3];
   __shared__ T s_y[OP == OP_VJP ? 1 : NN * 3];
   __shared__ T s_l[NEED_L ? NN * 3 : 1];
+  __shared__ T s_b[OP == OP_CG_APPLY ? NN * 3 : 1];  // CG: u on constrained dofs (A u = u there)
   __shared__ double s_red[6][EBLOCK / 64];
-  __shared__ double s_bc[2];
 
   if (stop && *stop) return;
   const int n = a.n;
@@ -546,47 +723,39 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
   const int nb = ntx * nty * ntz;
   const int per = (nb + 7) >> 3;
   const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  if (tile >= nb) {
-    // padding block of the XCD-aware numbering: still takes part in the p.Ap reduction
-    if (OP == OP_CG_APPLY && threadIdx.x == 0) a.cg_pa[blockIdx.x] = 0.0;
-    return;
-  }
+  if (tile >= nb) return;  // padding block of the XCD-aware numbering
   const int a0 = (tile % ntx) * TX, b0 = ((tile / ntx) % nty) * TY, c0 = (tile / (ntx * nty)) * TZ;
   const int tid = threadIdx.x;
   const T* X = static_cast<const T*>(a.x);
   const T* XL = static_cast<const T*>(a.xlin);
-  const T* CR = static_cast<const T*>(a.cg_r);
-  const T* CD = static_cast<const T*>(a.cg_dinv);
-  const T* CP = static_cast<const T*>(a.cg_pold);
-  T* CPN = static_cast<T*>(a.cg_pnew);
-  T cg_beta = T(0);
-  if (OP == OP_CG_APPLY) {  // direction step of this CG iteration (same decision in every workgroup)
-    double beta;
-    if (!cg_direction_step(a.ctrl, a.cg_pu, a.cg_k, &s_red[0][0], s_bc, beta)) return;
-    cg_beta = T(beta);
+  // single-reduction CG: alpha_{j-1}, beta_{j-1} from the slots of the previous launch
+  T cg_alpha = 0, cg_beta = 0;
+  if (OP == OP_CG_APPLY) {
+    if (blockIdx.x == 0)
+      for (int i = tid; i < 3 * CGS_SLOTS; i += EBLOCK) a.cg_acc_zero[i] = 0.0;  // slots of launch j+1
+    if (a.cg_j > 0 && !cg_scalars<T>(a, s_red, cg_alpha, cg_beta)) return;
   }
+  double cg_g = 0, cg_rr = 0;  // owners' shares of (r_j, u_j) and ||r_j||^2
   const int64_t np1 = n + 1;
 
-  for (int i = tid; i < NN * 3; i += EBLOCK) {
-    const int c = i % 3, nd = i / 3;
-    const int li = nd % NX, lj = (nd / NX) % NY, lk = nd / (NX * NY);
-    const int gi = a0 + li, gj = b0 + lj, gk = c0 + lk;
-    T v = 0, vl = 0;
-    if (gi <= n && gj <= n && gk <= n) {
-      const int64_t dof = 3 * (gi + np1 * (gj + np1 * gk)) + c;
-      if (OP == OP_CG_APPLY) {
-        // new search direction, formed identically by every brick that touches the node
-        v = pc_apply(CD, CR, dof, a.cg_block) + cg_beta * CP[dof];
-        if ((min(gi, n - 1) - a0 < TX) && (min(gj, n - 1) - b0 < TY) && (min(gk, n - 1) - c0 < TZ)) CPN[dof] = v;
-      } else {
+  if (OP == OP_CG_APPLY) {
+    cg_stage_brick<T, NEED_L>(a, n, a0, b0, c0, cg_alpha, cg_beta, s_x, s_y, s_b, s_l, cg_g, cg_rr);
+  } else {
+    for (int i = tid; i < NN * 3; i += EBLOCK) {
+      const int c = i % 3, nd = i / 3;
+      const int li = nd % NX, lj = (nd / NX) % NY, lk = nd / (NX * NY);
+      const int gi = a0 + li, gj = b0 + lj, gk = c0 + lk;
+      T v = 0, vl = 0;
+      if (gi <= n && gj <= n && gk <= n) {
+        const int64_t dof = 3 * (gi + np1 * (gj + np1 * gk)) + c;
         v = X[dof];
+        if (APPLY_LIKE && a.apply_bc && a.mask && a.mask[dof]) v = 0;
+        if (NEED_L) vl = XL[dof];
       }
-      if (APPLY_LIKE && a.apply_bc && a.mask && a.mask[dof]) v = 0;
-      if (NEED_L) vl = XL[dof];
+      s_x[i] = v;
+      if (OP != OP_VJP) s_y[i] = 0;
+      if (NEED_L) s_l[i] = vl;
     }
-    s_x[i] = v;
-    if (OP != OP_VJP) s_y[i] = 0;
-    if (NEED_L) s_l[i] = vl;
   }
   __syncthreads();
 
@@ -904,8 +1073,8 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
                       (gk == 0 || lk >= 1) && (gk == n || lk < TZ);
     if (a.apply_bc && a.mask && a.mask[dof]) {
       if (own) {
-        if (OP == OP_CG_APPLY) {  // A p = p on constrained dofs; their p.Ap share is p^2
-          const T v = pc_apply(CD, CR, dof, a.cg_block) + cg_beta * CP[dof];
+        if (OP == OP_CG_APPLY) {  // A u = u on constrained dofs; their (u, A u) share is u^2
+          const T v = s_b[i];
           Y[dof] = v;
           pq += (double)v * (double)v;
         } else {
@@ -919,9 +1088,16 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
     else
       atomic_add(Y + dof, s_y[i]);
   }
-  if (OP == OP_CG_APPLY) {
-    const double t = block_sum(pq, &s_red[0][0]);
-    if (threadIdx.x == 0) a.cg_pa[blockIdx.x] = t;
+  if (OP == OP_CG_APPLY) {  // partials of (u_j, A u_j), (r_j, u_j), ||r_j||^2
+    const double t0 = block_sum(pq, &s_red[0][0]);
+    const double t1 = block_sum(cg_g, &s_red[0][0]);
+    const double t2 = block_sum(cg_rr, &s_red[0][0]);
+    if (threadIdx.x == 0) {  // workgroups share CGS_SLOTS slots per quantity
+      const int sl = (int)(blockIdx.x % CGS_SLOTS);
+      atomic_add(a.cg_acc_out + sl, t0);
+      atomic_add(a.cg_acc_out + CGS_SLOTS + sl, t1);
+      atomic_add(a.cg_acc_out + 2 * CGS_SLOTS + sl, t2);
+    }
   }
 }
 
@@ -1880,6 +2056,63 @@ static hipError_t cg_operator_t(const fe_problem* p, int op, const int32_t* rp, 
                        (const T*)p->w_p, Q, stop, pa);
     return hipGetLastError();
   }
+  return hipErrorInvalidValue;  // the matrix-free operator runs through cgs_operator
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-free CG with one operator launch per iteration (single-reduction form of
+// Chronopoulos & Gear 1989; exact-arithmetic equivalent of the CG recursion):
+//   launch j forms u_j = M^-1 r_j, w_j = A u_j and the partials of (u_j, w_j),
+//   (r_j, u_j), ||r_j||^2; its staging applies update j-1 (see cg_stage) and its last
+//   workgroup reduces the partials into alpha_j, beta_j or a stop (see cg_finish).
+// Vectors: x (caller), p (in place, owners only), r in two buffers, s in two, w in three
+// (launch j writes w into the buffer that launch j-1 zeroed).
+
+template <typename T> __global__ __launch_bounds__(VBLOCK) void cgs_init_kernel(
+    int64_t n, const T* b, T* x, T* r0, T* p, T* s1, T* w0, T* dinv, int block, CgCtrl* ctrl, double rtol,
+    int max_it, double* acc0) {
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < 3 * CGS_SLOTS; i += VBLOCK) acc0[i] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * VBLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * VBLOCK) {
+    x[i] = 0;
+    r0[i] = b[i];
+    p[i] = 0;
+    s1[i] = 0;
+    w0[i] = 0;
+    if (!block) dinv[i] = T(1) / dinv[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl->rtol2 = rtol * rtol;
+    ctrl->iters = 0;
+    ctrl->max_it = max_it;
+    ctrl->alpha = ctrl->beta = ctrl->pq = 0;
+    ctrl->ghist[0] = ctrl->ghist[1] = ctrl->ahist[0] = ctrl->ahist[1] = 0;
+    ctrl->status = CG_RUNNING;
+  }
+}
+
+template <typename T> static T* cgs_vec(const fe_problem* p, int k) {  // 0 r_1, 1 s_0, 2 s_1, 3 w_0, 4 w_1, 5 w_2
+  return static_cast<T*>(p->w_cg) + (int64_t)k * p->n_dof;
+}
+
+template <typename T> static T* cgs_r(const fe_problem* p, long j) { return (j & 1) ? cgs_vec<T>(p, 0) : (T*)p->w_r; }
+template <typename T> static T* cgs_s(const fe_problem* p, long j) { return cgs_vec<T>(p, 1 + (int)(j & 1)); }
+template <typename T> static T* cgs_w(const fe_problem* p, long j) { return cgs_vec<T>(p, 3 + (int)(j % 3)); }
+
+template <typename T>
+static hipError_t cgs_init_t(const fe_problem* p, const T* b, T* x, double rtol, int max_it, hipStream_t s) {
+  hipLaunchKernelGGL(cgs_init_kernel<T>, dim3(CG_UGRID), dim3(VBLOCK), 0, s, p->n_dof, b, x, (T*)p->w_r,
+                     (T*)p->w_p, cgs_s<T>(p, 1), cgs_w<T>(p, 0), (T*)pc_buffer(p), p->precond, p->ctrl, rtol,
+                     max_it, p->partials);
+  return hipGetLastError();
+}
+
+hipError_t cgs_init(const fe_problem* p, const void* b, void* x, double rtol, int max_it, hipStream_t s) {
+  return p->prec == FE_F64 ? cgs_init_t(p, (const double*)b, (double*)x, rtol, max_it, s)
+                           : cgs_init_t(p, (const float*)b, (float*)x, rtol, max_it, s);
+}
+
+template <typename T> static hipError_t cgs_operator_t(const fe_problem* p, T* x, long j, hipStream_t s) {
   ElemArgs a{};
   a.n = p->n;
   a.h = p->h;
@@ -1888,22 +2121,34 @@ static hipError_t cg_operator_t(const fe_problem* p, int op, const int32_t* rp, 
   a.scale = p->scale;
   a.mask = p->mask;
   a.xlin = p->u_lin;
-  a.y = Q;
   a.tangent = p->tangent;
   a.apply_bc = 1;
   a.mat = p->mat;
   a.sur_map = p->sur_map;
   a.sur_D = p->sur_D;
-  a.cg_r = p->w_r;
   a.cg_dinv = pc_buffer(p);
   a.cg_block = p->precond;
-  a.cg_pnew = cg_p_new(p, op, k);
-  a.cg_pold = (a.cg_pnew == p->w_p) ? p->w_p2 : p->w_p;
   a.ctrl = p->ctrl;
-  a.cg_pa = pa;
-  a.cg_pu = p->partials + cg_pa_size(p);
-  a.cg_k = k;
-  return launch_elem_t<T, OP_CG_APPLY>(p, a, stop, s);
+  a.cg_j = j;
+  // launch j: reads r_{j-1} (r_0 = b at j = 0), w_{j-1}, s_{j-2}; writes r_j, s_{j-1}, w_j
+  a.cg_rold = j == 0 ? (const void*)p->w_r : cgs_r<T>(p, j - 1);
+  a.cg_rnew = cgs_r<T>(p, j);
+  a.cg_wold = j == 0 ? nullptr : cgs_w<T>(p, j - 1);
+  a.cg_sold = j == 0 ? nullptr : cgs_s<T>(p, j);  // s_{j-2} lives in the slot of parity j
+  a.cg_snew = j == 0 ? nullptr : cgs_s<T>(p, j - 1);
+  a.cg_wzero = cgs_w<T>(p, j + 1);
+  a.y = cgs_w<T>(p, j);
+  a.cg_pvec = p->w_p;
+  a.cg_x = x;
+  double* acc = p->partials;  // three sets of 3 * CGS_SLOTS, cycled over launches
+  a.cg_acc_in = j == 0 ? nullptr : acc + ((j + 2) % 3) * 3 * CGS_SLOTS;
+  a.cg_acc_out = acc + (j % 3) * 3 * CGS_SLOTS;
+  a.cg_acc_zero = acc + ((j + 1) % 3) * 3 * CGS_SLOTS;
+  return launch_elem_t<T, OP_CG_APPLY>(p, a, &p->ctrl->status, s);
+}
+
+hipError_t cgs_operator(const fe_problem* p, void* x, long j, hipStream_t s) {
+  return p->prec == FE_F64 ? cgs_operator_t(p, (double*)x, j, s) : cgs_operator_t(p, (float*)x, j, s);
 }
 
 hipError_t cg_operator(const fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, long k,

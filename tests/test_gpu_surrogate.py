@@ -137,12 +137,16 @@ def test_surrogate_newton_end_to_end():
     network: the ramp converges and its homogenised stress stays within 1e-3 of the
     return-map ramp (the local check sends poorly predicted points back to the return
     map).  Timings, accepted fraction and the error are printed: this is what the network
-    gains (or costs) against the method without it at this size."""
+    gains (or costs) against the method without it at this size.  The captured sample set
+    varies slightly between runs (face atomics reorder sums), and with it the network and the
+    Newton iteration count of the surrogate ramp (20 to 50 over the five steps), hence the
+    generous per-step iteration limit."""
     import time
     import torch
     from paper_2604_22087_amd import fe
     from paper_2604_22087_amd import surrogate as gsur
     n = 16
+    torch.manual_seed(0)
     P = gsur.fiber_problem(n)
     x, y = gsur.capture_samples([(P, gsur.ramp(0.03, 10), 1), (P, gsur.ramp(0.03, 10, shear=True), 1)],
                                 capacity=4_000_000)
@@ -157,7 +161,7 @@ def test_surrogate_newton_end_to_end():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, _, sig, info = P.newton(gsur.ramp(0.02, 5), state=P.state(), op=fe.OP_MATFREE, newton_rtol=1e-8,
-                                   pcg_rtol=1e-10, max_newton=30)
+                                   pcg_rtol=1e-10, max_newton=60)
         torch.cuda.synchronize()
         res[mode] = (time.perf_counter() - t0, np.array(sig), info,
                      P.surrogate_stats() if mode == "surrogate" else None)
