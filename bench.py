@@ -37,6 +37,11 @@ FIBER = (230.0, 0.2)
 MATRIX = (3.5, 0.35, 0.05, 0.1)
 
 
+# inside the timed region only every k-th CG operator launch carries an event pair (each
+# pair costs several microseconds of issue time, about 10% of a 64^3 iteration)
+CG_TIMING_STRIDE = 16
+
+
 def measured_traffic():
     """HBM bytes per launch of the fused CG operator from the committed rocprofv3 counter runs
     (FETCH_SIZE / WRITE_SIZE, scaled by a 1 GiB copy), or None when the kernel source has
@@ -146,7 +151,7 @@ def neohooke_leg(n):
         u, state = P.vector(), P.state()
         f64 = prec == "f64"
         torch.cuda.synchronize()
-        P.profile(True)
+        P.profile(CG_TIMING_STRIDE)
         t0 = time.perf_counter()
         _, _, sig, info = P.newton(path, u=u, state=state, op=fe.OP_MATFREE, newton_rtol=1e-8 if f64 else 1e-5,
                                    pcg_rtol=1e-10 if f64 else 1e-6, max_newton=30)
@@ -188,7 +193,7 @@ def surrogate_leg(n):
             P.set_surrogate(W, fallback_tol=1e-3)
         u, st = P.vector(), P.state()
         torch.cuda.synchronize()
-        P.profile(True)
+        P.profile(CG_TIMING_STRIDE)
         t0 = time.perf_counter()
         _, _, sig, info = P.newton(S.ramp(0.02, 10), u=u, state=st, op=fe.OP_MATFREE, newton_rtol=1e-6,
                                    pcg_rtol=1e-8, max_newton=30, check=False)
@@ -329,7 +334,7 @@ def main():
     for _ in range(args.warmup):
         run_ramp(P, u, state, path)
     torch.cuda.synchronize()
-    P.profile(True)
+    P.profile(CG_TIMING_STRIDE)
     infos = []
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -369,6 +374,8 @@ def main():
                      "kernel": "elem_kernel<double, OP_CG_APPLY, MS_J2> (CG direction step fused with the "
                                "matrix-free K*u)",
                      "avg_launch_us": 1e3 * ku_avg_ms, "launches": cnt,
+                     "sampling": f"HIP event pairs on operator launches 0, {CG_TIMING_STRIDE}, "
+                                 f"{2 * CG_TIMING_STRIDE}, ... of every CG solve in the timed region",
                      "bytes_per_launch": byts / max(cnt, 1)},
         "ku_kernel_gdofs": P.n_dof / (ku_avg_ms * 1e-3) / 1e9,
         "qp_evals_per_s": P.n_qp / (rms / max(rcnt, 1) * 1e-3),

@@ -239,7 +239,10 @@ int fe_mean_stress(fe_problem* p, const void* u, const void* state_in, double* s
  * (fe_apply_csr and inside CG), class 2 the residual / return-map element
  * kernel, class 3 the CSR tangent kernel, class 4 the node-structured CSR
  * mat-vec (fe_apply_csr_nodal).  enable = 1 clears previous records; enable = 0
- * stops recording.  fe_profile_read synchronises the device and writes, for
+ * stops recording; enable = k > 1 is enable = 1 except that inside a CG solve
+ * only operator launches 0, k, 2k, ... are timed (an event pair costs several
+ * microseconds of issue time per launch); enable < 0 is FE_ERR_ARG.
+ * fe_profile_read synchronises the device and writes, for
  * c = 0..4, out_host[3*c] = launches, out_host[3*c+1] = summed milliseconds,
  * out_host[3*c+2] = summed algorithmic bytes of those launches for classes 0, 1
  * and 4 (compulsory traffic: x read and y written once, phase ids, the stored

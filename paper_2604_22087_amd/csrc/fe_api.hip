@@ -542,17 +542,26 @@ static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, 
   }
   const size_t rec0 = p->prof_recs.size();
   const int cls = op == FE_OP_CSR ? 1 : 0;
+  const long stride = p->prof ? p->prof_stride : 1;
+  long n_op = 0;  // operator launches of this solve; every stride-th one is timed
+#define CG_OPERATOR(expr)                \
+  do {                                   \
+    if (n_op++ % stride == 0)            \
+      PROF(p, s, cls, expr);             \
+    else                                 \
+      HIPCHK(expr);                      \
+  } while (0)
   int launched = 0, chunk = 8;
   long k = 0;
-  if (fused) PROF(p, s, cls, cgs_operator(p, x, 0, s));
+  if (fused) CG_OPERATOR(cgs_operator(p, x, 0, s));
   for (;;) {
     for (int c = 0; c < chunk; ++c, ++k) {
       if (fused) {
-        PROF(p, s, cls, cgs_operator(p, x, k + 1, s));
+        CG_OPERATOR(cgs_operator(p, x, k + 1, s));
         continue;
       }
       HIPCHK(cg_pre(p, op, k, s));
-      PROF(p, s, cls, cg_operator(p, op, rp, ci, vals, k, s));
+      CG_OPERATOR(cg_operator(p, op, rp, ci, vals, k, s));
       HIPCHK(cg_vectors(p, op, x, k, s));
     }
     launched += chunk;
@@ -567,14 +576,17 @@ static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, 
   // (the fused form runs one launch more than iterations: launch j forms u_j = M^-1 r_j)
   const size_t executed = (size_t)c.iters + (fused ? 1 : 0) +
                           (!fused && (status == FE_ERR_BREAKDOWN || status == FE_ERR_NONFINITE) ? 1 : 0);
-  if (p->prof) {
-    if (p->prof_recs.size() > rec0 + executed) p->prof_recs.resize(rec0 + executed);
+#undef CG_OPERATOR
+  if (p->prof) {  // timed launches among the executed ones: 0, stride, 2 stride, ...
+    const size_t kept = (executed + (size_t)stride - 1) / (size_t)stride;
+    if (p->prof_recs.size() > rec0 + kept) p->prof_recs.resize(rec0 + kept);
+    const size_t timed = p->prof_recs.size() - rec0;
     double b = 0;
     if (int e = operator_bytes(p, op, s, &b)) return e;
     // the fused matrix-free CG launch reads r, w, s, p, x and M^-1 (1 or 2 reals per dof)
     // and writes r, s, p, x and the zeroed w instead of reading x
     if (fused) b += (p->precond == FE_PC_BLOCK_JACOBI ? 11.0 : 10.0) * (double)real_size(p) * (double)p->n_dof;
-    p->prof_bytes[cls] += b * (double)executed;
+    p->prof_bytes[cls] += b * (double)timed;
   }
   if (info) {
     info->iterations = c.iters;
@@ -840,9 +852,11 @@ extern "C" int fe_newton(fe_problem* p, const double* path, int n_steps, const f
 
 extern "C" int fe_profile(fe_problem* p, int enable) {
   CHKP(p);
+  if (enable < 0) return arg_error("enable must be >= 0");
   if (enable) {
     p->prof_recs.clear();
     p->ev_used = 0;
+    p->prof_stride = enable;
   }
   p->prof = enable != 0;
   return FE_OK;

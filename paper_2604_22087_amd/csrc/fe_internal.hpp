@@ -191,6 +191,7 @@ struct fe_problem {
   unsigned int cap_stride = 1, cap_salt = 0;
   // kernel timing (fe_profile): event pairs around selected launches
   bool prof = false;
+  int prof_stride = 1;  // inside CG: time operator launches 0, k, 2k, ... of each solve
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, size_t>> prof_recs;  // (kernel class, index of the start event)
   size_t ev_used = 0;

@@ -740,21 +740,29 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
 
   if (OP == OP_CG_APPLY) {
     cg_stage_brick<T, NEED_L>(a, n, a0, b0, c0, cg_alpha, cg_beta, s_x, s_y, s_b, s_l, cg_g, cg_rr);
-  } else {
-    for (int i = tid; i < NN * 3; i += EBLOCK) {
+  } else {  // all loads of the lane first, then the LDS stores
+    T v[STAGE_IT], vl[STAGE_IT];
+    bool fx[STAGE_IT];
+    const bool bc = APPLY_LIKE && a.apply_bc && a.mask;
+#pragma unroll
+    for (int t = 0; t < STAGE_IT; ++t) {
+      const int i = tid + t * EBLOCK;
       const int c = i % 3, nd = i / 3;
       const int li = nd % NX, lj = (nd / NX) % NY, lk = nd / (NX * NY);
       const int gi = a0 + li, gj = b0 + lj, gk = c0 + lk;
-      T v = 0, vl = 0;
-      if (gi <= n && gj <= n && gk <= n) {
-        const int64_t dof = 3 * (gi + np1 * (gj + np1 * gk)) + c;
-        v = X[dof];
-        if (APPLY_LIKE && a.apply_bc && a.mask && a.mask[dof]) v = 0;
-        if (NEED_L) vl = XL[dof];
-      }
-      s_x[i] = v;
+      const bool in = i < NN * 3 && gi <= n && gj <= n && gk <= n;
+      const int64_t dof = 3 * (gi + np1 * (gj + np1 * gk)) + c;
+      v[t] = in ? X[dof] : T(0);
+      vl[t] = NEED_L && in ? XL[dof] : T(0);
+      fx[t] = bc && in && a.mask[dof];
+    }
+#pragma unroll
+    for (int t = 0; t < STAGE_IT; ++t) {
+      const int i = tid + t * EBLOCK;
+      if (i >= NN * 3) break;
+      s_x[i] = fx[t] ? T(0) : v[t];
       if (OP != OP_VJP) s_y[i] = 0;
-      if (NEED_L) s_l[i] = vl;
+      if (NEED_L) s_l[i] = vl[t];
     }
   }
   __syncthreads();

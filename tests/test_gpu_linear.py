@@ -122,6 +122,39 @@ def test_config1_solve_matches_oracle(op):
     assert rel_err(sig[0], sbar) <= 1e-8
 
 
+@pytest.mark.parametrize("op", ["matfree", "csr"])
+def test_profile_sampling_inside_cg(op):
+    """Timing records inside a CG solve: every executed operator launch with enable = 1
+    (the fused matrix-free solve runs one launch more than iterations), launches 0, k, 2k, ...
+    with enable = k; the algorithmic bytes per recorded launch are the same."""
+    import math
+    import torch
+    from paper_2604_22087_amd import fe
+    n = 8
+    print(f"[profile sampling] op={op}", flush=True)
+    P = _problem(n, "f64", inputs.sphere_phase(n))
+    P.set_dirichlet(torch.tensor(inputs.boundary_dof_mask(n), device="cuda"))
+    u = P.vector()
+    P.lift(np.diag([0.01, 0.0, 0.0]), u, zero_free=True)
+    b = P.residual(u, apply_bc=True, store_tangent=True)
+    b.neg_()
+    kw = dict(op=fe.OP_MATFREE) if op == "matfree" else \
+        dict(op=fe.OP_CSR, csr=(*P.csr_indices(), P.tangent_csr(u, apply_bc=True)))
+    cls = "matfree_apply" if op == "matfree" else "csr_spmv"
+    rec = {}
+    for k in (1, 4):
+        P.profile(k)
+        _, res = P.pcg(b, rtol=1e-10, **kw)
+        rec[k] = P.profile_read()[cls]
+        P.profile(False)
+    executed = res.iterations + (1 if op == "matfree" else 0)
+    assert rec[1][0] == executed
+    assert rec[4][0] == math.ceil(executed / 4)
+    assert rec[1][2] / rec[1][0] == pytest.approx(rec[4][2] / rec[4][0], rel=1e-12)
+    with pytest.raises(fe.FeError):
+        P.profile(-1)
+
+
 def test_scale_field_and_vjp():
     """Per-element modulus scale; vjp_e = lambda_e . K_hat_e u_e against the oracle."""
     n = 6
