@@ -10,6 +10,10 @@ relative residual tolerance.  The CG recursion is the textbook one
 alpha = (r.z)/(p.q), x += alpha p, r -= alpha q, stop when ||r||_2 <= rtol ||b||_2,
 z = M^-1 r, beta = (r.z)_new/(r.z)_old, p = z + beta p.  M = diag(A).
 
+Fig. 4 also runs GMRES and BiCGStab on the same systems; both are kept here for
+nonsymmetric operators (right preconditioning, so the stopping test is on the
+unpreconditioned residual like CG's).
+
 Sec. V-B (Fig. 7) compares point Jacobi with stronger preconditioning of the
 assembled matrix.  The first step beyond point Jacobi kept here is node-block
 Jacobi: M = the 3x3 blocks of A that couple the three displacement components
@@ -172,5 +176,85 @@ def bicgstab(apply_a, b, rtol, max_it, precond=None):
         if np.linalg.norm(r) <= rtol * bnorm:
             status = OK
             break
+    true_rel = np.linalg.norm(b - apply_a(x)) / bnorm
+    return x, it, status, true_rel
+
+
+def gmres(apply_a, b, rtol, max_it, restart=30, precond=None):
+    """Right-preconditioned restarted GMRES(m) (Saad & Schultz 1986; Saad, Iterative
+    Methods for Sparse Linear Systems, 2003, Alg. 6.9 with right preconditioning,
+    Sec. 9.3.2), x0 = 0.  A cycle builds an orthonormal basis v_0..v_k of the Krylov
+    space of A M^-1 from v_0 = r/||r|| by Arnoldi with modified Gram-Schmidt, reduces
+    the Hessenberg matrix to triangular form with Givens rotations applied to
+    g = ||r|| e_1, and stops when |g_{k}| (the residual norm of the least-squares
+    iterate) <= rtol ||b||_2.  After m steps without convergence the iterate
+    x += M^-1 V y (y from the triangular system) is formed and the cycle restarts
+    from the true residual b - A x.  One iteration = one Arnoldi step (one operator
+    application).  Returns (x, iterations, status, true relative residual)."""
+    minv = precond if precond is not None else (lambda v: v)
+    m = int(restart)
+    x = np.zeros_like(b)
+    bnorm = np.linalg.norm(b)
+    if not np.all(np.isfinite(b)):
+        return x, 0, NONFINITE, np.nan
+    if bnorm == 0.0:
+        return x, 0, OK, 0.0
+    tol = rtol * bnorm
+    it, status = 0, NOT_CONVERGED
+    r = b.copy()
+    while True:
+        beta = np.linalg.norm(r)
+        if beta <= tol:
+            status = OK
+            break
+        if it >= max_it:
+            break
+        V = np.zeros((m + 1, b.size))
+        H = np.zeros((m + 1, m))
+        cs, sn = np.zeros(m), np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        V[0] = r / beta
+        k, stop = 0, None
+        for j in range(m):
+            w = apply_a(minv(V[j]))
+            for i in range(j + 1):          # modified Gram-Schmidt
+                H[i, j] = V[i] @ w
+                w = w - H[i, j] * V[i]
+            h_next = np.linalg.norm(w)
+            H[j + 1, j] = h_next
+            if not np.isfinite(h_next):
+                stop = NONFINITE
+                break
+            for i in range(j):              # earlier rotations on the new column
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            rho = np.hypot(H[j, j], H[j + 1, j])
+            if rho == 0.0:                  # singular least-squares problem
+                stop = BREAKDOWN
+                break
+            cs[j], sn[j] = H[j, j] / rho, H[j + 1, j] / rho
+            H[j, j], H[j + 1, j] = rho, 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            it += 1
+            k = j + 1
+            if abs(g[j + 1]) <= tol:
+                stop = OK
+                break
+            if it >= max_it:
+                stop = NOT_CONVERGED
+                break
+            V[j + 1] = w / h_next
+        if k > 0:
+            y = np.zeros(k)                 # back substitution on the triangular block
+            for i in range(k - 1, -1, -1):
+                y[i] = (g[i] - H[i, i + 1:k] @ y[i + 1:k]) / H[i, i]
+            x += minv(V[:k].T @ y)
+        if stop is not None:
+            status = stop
+            break
+        r = b - apply_a(x)
     true_rel = np.linalg.norm(b - apply_a(x)) / bnorm
     return x, it, status, true_rel
