@@ -61,7 +61,7 @@ enum { FE_F64 = 0, FE_F32 = 1 };                      /* precision of real array
 enum { FE_LINEAR = 0, FE_J2 = 1, FE_NEOHOOKE = 2 };    /* constitutive model per phase */
 enum { FE_OP_CSR = 0, FE_OP_MATFREE = 1 };             /* operator used by fe_pcg / fe_newton */
 enum { FE_PC_JACOBI = 0, FE_PC_BLOCK_JACOBI = 1 };     /* CG preconditioner (fe_set_preconditioner) */
-enum { FE_SOLVER_CG = 0, FE_SOLVER_BICGSTAB = 1 };     /* Krylov method of fe_newton's inner solves */
+enum { FE_SOLVER_CG = 0, FE_SOLVER_BICGSTAB = 1, FE_SOLVER_GMRES = 2 };  /* Krylov method of fe_newton's inner solves */
 enum { FE_APPLY_BC = 1, FE_STORE_TANGENT = 2 };        /* fe_residual flags */
 enum { FE_MAX_PHASES = 8 };
 
@@ -83,7 +83,8 @@ typedef struct {
   double newton_rtol;    /* stop when ||P_f R|| <= newton_rtol * ||P_f R||_first (e.g. 1e-8) */
   double pcg_rtol;       /* inner CG tolerance (e.g. 1e-10) */
   int pcg_max_it;        /* inner CG iteration limit */
-  int solver;            /* FE_SOLVER_CG (symmetric tangents) or FE_SOLVER_BICGSTAB */
+  int solver;            /* FE_SOLVER_CG (symmetric tangents), FE_SOLVER_BICGSTAB or FE_SOLVER_GMRES */
+  int restart;           /* GMRES restart length (1..64; 0 = 30) */
 } fe_newton_opts;
 
 typedef struct {
@@ -194,6 +195,21 @@ int fe_pcg(fe_problem* p, int op, const int32_t* row_ptr, const int32_t* col_idx
 int fe_bicgstab(fe_problem* p, int op, const int32_t* row_ptr, const int32_t* col_idx,
                 const void* vals, const void* b, void* x, double rtol, int max_it,
                 fe_pcg_info* info_host, void* stream);
+
+/* Restarted GMRES(m) on A x = b (Saad & Schultz 1986; Fig. 4 of the paper compares
+ * it with CG and BiCGStab), right-preconditioned by the preconditioner of
+ * fe_set_preconditioner: same operators and arguments as fe_pcg, x0 = 0, stops
+ * when the least-squares residual estimate |g_k| <= rtol ||b||_2 (info relres is
+ * that estimate over ||b||); after `restart` Arnoldi steps (1..64, else
+ * FE_ERR_ARG) x is updated and the next cycle starts from b - A x.  One iteration
+ * = one Arnoldi step = one application of A.  Returns FE_OK,
+ * FE_ERR_NOT_CONVERGED (max_it steps; x holds the last least-squares iterate),
+ * FE_ERR_BREAKDOWN (singular Hessenberg block) or FE_ERR_NONFINITE.  Workspace of
+ * restart + 3 vectors allocated on first use or when a longer restart is asked
+ * for (FE_ERR_OOM if that fails). */
+int fe_gmres(fe_problem* p, int op, const int32_t* row_ptr, const int32_t* col_idx,
+             const void* vals, const void* b, void* x, double rtol, int max_it, int restart,
+             fe_pcg_info* info_host, void* stream);
 
 /* Vector-Jacobian product with respect to the per-element modulus scale s_e:
  * out[e] = lambda_e^T d r_e / d s_e, real [n_el].  Supported for linear and

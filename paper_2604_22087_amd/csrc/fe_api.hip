@@ -136,6 +136,9 @@ void fe_problem_destroy(fe_problem* p) {
   free_dev(p->w_blk);
   free_dev(p->w_bicg);
   free_dev(p->w_cg);
+  free_dev(p->w_gm);
+  free_dev(p->gm_dev);
+  free_dev(p->gm_part);
   free_dev(p->bicg_part);
   free_dev(p->bicg_ctrl);
   free_dev(p->w_v);
@@ -662,6 +665,100 @@ static int bicg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci,
   return status;
 }
 
+// Restarted GMRES(m) driver: the host enqueues Arnoldi steps in chunks and polls the
+// device status between chunks; a cycle ends after m steps or at a stop, then
+// x += M^-1 V y runs and, unless stopped, the next cycle starts from b - A x.
+static int gmres_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, const void* b,
+                     void* x, double rtol, int max_it, int m, fe_pcg_info* info, hipStream_t s, int* applies) {
+  const size_t rs = real_size(p);
+  if (p->w_gm && p->gm_cap < m) {
+    free_dev(p->w_gm);
+    p->w_gm = nullptr;
+  }
+  if (!p->w_gm) {
+    if (int st = alloc(&p->w_gm, (size_t)(m + 3) * rs * (size_t)p->n_dof)) return st;
+    p->gm_cap = m;
+  }
+  if (!p->gm_dev && alloc((void**)&p->gm_dev, sizeof(GmresDev))) return FE_ERR_OOM;
+  if (!p->gm_part && alloc((void**)&p->gm_part, (size_t)(GM_MAXM + 1) * GM_GRID * sizeof(double)))
+    return FE_ERR_OOM;
+  if (p->precond == FE_PC_BLOCK_JACOBI) {
+    HIPCHK(launch_block_jacobi(p, rp, ci, vals, p->w_blk, s));
+  } else if (rp) {
+    HIPCHK(launch_csr_diag(p, rp, ci, vals, p->w_d, s));
+  } else {
+    HIPCHK(launch_diag(p, p->w_d, 1, s));
+  }
+  const int* stop = &p->gm_dev->ctrl.status;
+  auto apply = [&](const void* in, void* out, const int* stp) -> hipError_t {
+    if (op == FE_OP_CSR) return launch_spmv_stop(p, rp, ci, vals, in, out, stp, s);
+    ElemArgs a = base_args(p);
+    a.x = in;
+    a.xlin = p->u_lin;
+    a.y = out;
+    a.apply_bc = 1;
+    return launch_elem_stop(p, OP_APPLY, a, stp, s);
+  };
+  GmresCtrl* hc = reinterpret_cast<GmresCtrl*>(p->host_buf);
+  static_assert(sizeof(GmresCtrl) <= 64 * sizeof(double), "host scratch too small");
+  auto poll = [&]() -> int {
+    HIPCHK(hipMemcpyAsync(hc, &p->gm_dev->ctrl, sizeof(GmresCtrl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return FE_OK;
+  };
+  HIPCHK(gm_setup(p, b, x, rtol, max_it, m, s));
+  HIPCHK(gm_step(p, GM_START, 0, b, x, s));
+  int restarts = 0;
+  for (;;) {
+    if (int e = poll()) return e;
+    if (hc->status != CG_RUNNING) break;
+    int j = 0, chunk = 4;
+    while (j < m) {
+      for (int c = 0; c < chunk && j < m; ++c, ++j) {
+        HIPCHK(gm_step(p, GM_BASIS, j, b, x, s));
+        HIPCHK(apply(gm_work_z(p), gm_work_w(p), stop));
+        HIPCHK(gm_step(p, GM_ORTHO, j, b, x, s));
+      }
+      if (int e = poll()) return e;
+      if (hc->status != CG_RUNNING) break;
+      if (chunk < 16) chunk *= 2;
+    }
+    HIPCHK(gm_step(p, GM_FINISH, 0, b, x, s));
+    if (int e = poll()) return e;
+    if (hc->status != CG_RUNNING) break;
+    HIPCHK(apply(x, gm_work_w(p), nullptr));  // next cycle: w = b - A x
+    HIPCHK(gm_step(p, GM_RESIDUAL, 0, b, x, s));
+    ++restarts;
+  }
+  const int status = hc->status == CG_CONVERGED ? FE_OK : hc->status;
+  if (info) {
+    info->iterations = hc->iters;
+    info->status = status;
+    info->bnorm = hc->bb > 0 ? std::sqrt(hc->bb) : 0.0;
+    info->relres = hc->bb > 0 ? hc->res_est / std::sqrt(hc->bb) : 0.0;
+  }
+  if (applies) *applies += hc->iters + restarts;
+  if (status != FE_OK) set_error(fe_status_string(status));
+  return status;
+}
+
+extern "C" int fe_gmres(fe_problem* p, int op, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
+                        const void* b, void* x, double rtol, int max_it, int restart, fe_pcg_info* info,
+                        void* stream) {
+  CHKP(p);
+  if (!b || !x) return arg_error("b and x are required");
+  if (op != FE_OP_CSR && op != FE_OP_MATFREE) return arg_error("op must be FE_OP_CSR or FE_OP_MATFREE");
+  if (op == FE_OP_CSR && (!row_ptr || !col_idx || !vals)) return arg_error("CSR operator needs row_ptr, col_idx, vals");
+  if (op == FE_OP_MATFREE && !p->lin_valid) {
+    set_error("no linearisation stored");
+    return FE_ERR_STATE;
+  }
+  if (!(rtol >= 0) || max_it < 0) return arg_error("rtol must be >= 0 and max_it >= 0");
+  if (restart < 1 || restart > GM_MAXM) return arg_error("restart must be in [1, 64]");
+  if (op == FE_OP_MATFREE) row_ptr = nullptr, col_idx = nullptr, vals = nullptr;
+  return gmres_run(p, op, row_ptr, col_idx, vals, b, x, rtol, max_it, restart, info, S(stream), nullptr);
+}
+
 extern "C" int fe_bicgstab(fe_problem* p, int op, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
                            const void* b, void* x, double rtol, int max_it, fe_pcg_info* info, void* stream) {
   CHKP(p);
@@ -741,6 +838,8 @@ extern "C" int fe_newton(fe_problem* p, const double* path, int n_steps, const f
   if (o->op != FE_OP_CSR && o->op != FE_OP_MATFREE) return arg_error("opts.op must be FE_OP_CSR or FE_OP_MATFREE");
   if (o->max_newton < 1 || !(o->newton_rtol >= 0) || !(o->pcg_rtol >= 0) || o->pcg_max_it < 1)
     return arg_error("invalid Newton options");
+  if (o->solver < FE_SOLVER_CG || o->solver > FE_SOLVER_GMRES) return arg_error("opts.solver is not a solver");
+  if (o->restart < 0 || o->restart > GM_MAXM) return arg_error("opts.restart must be in [0, 64]");
   if (p->model_set == MS_J2 && !state) return arg_error("J2 problems need a state array");
   hipStream_t s = S(stream);
   const size_t rs = real_size(p), vec = rs * p->n_dof;
@@ -806,7 +905,10 @@ extern "C" int fe_newton(fe_problem* p, const double* path, int n_steps, const f
         vals = p->csr_v;
       }
       fe_pcg_info pi{};
-      st = o->solver == FE_SOLVER_BICGSTAB
+      st = o->solver == FE_SOLVER_GMRES
+               ? gmres_run(p, o->op, rp, ci, vals, r, w, o->pcg_rtol, o->pcg_max_it,
+                           o->restart > 0 ? o->restart : 30, &pi, s, &inf.operator_applies)
+           : o->solver == FE_SOLVER_BICGSTAB
                ? bicg_run(p, o->op, rp, ci, vals, r, w, o->pcg_rtol, o->pcg_max_it, &pi, s, &inf.operator_applies)
                : pcg_run(p, o->op, rp, ci, vals, r, w, o->pcg_rtol, o->pcg_max_it, &pi, s, &inf.operator_applies);
       inf.pcg_iterations += pi.iterations;

@@ -49,6 +49,34 @@ constexpr int CG_UGRID = 512;        // workgroups of the CG vector kernels (= u
 constexpr int SPMV_MAXGRID = 2048;   // workgroups of the CG mat-vec (grid-stride over rows)
 
 // Device scalar block used by CG (one per problem).
+// restarted GMRES (fe_krylov.hip)
+constexpr int GM_MAXM = 64;   // longest restart cycle
+constexpr int GM_GRID = 512;  // workgroups of the GMRES vector kernels (= partial slots per vector)
+
+struct GmresCtrl {
+  double rtol, tol;  // tol = rtol ||b|| (set at the first cycle start)
+  double bb;         // ||b||^2 (-1 until the first cycle start)
+  double res_est;    // |g_k|: residual norm of the current least-squares iterate
+  double inv_norm;   // 1 / ||w|| for the next basis vector
+  int status;        // CG_RUNNING, CG_CONVERGED or an fe_status error code
+  int iters;         // Arnoldi steps over all cycles
+  int max_it;
+  int k;             // finished columns of the running cycle
+  int m;             // restart length
+  int cycles;
+};
+
+struct GmresDev {
+  GmresCtrl ctrl;
+  double H[GM_MAXM][GM_MAXM + 1];  // Hessenberg matrix by columns (rotated to triangular form)
+  double cs[GM_MAXM], sn[GM_MAXM];
+  double g[GM_MAXM + 1];
+  double y[GM_MAXM];
+  double c[2][GM_MAXM + 1];        // Gram-Schmidt coefficients of the two passes
+};
+
+enum GmStage { GM_START = 1, GM_BASIS, GM_ORTHO, GM_FINISH, GM_RESIDUAL };
+
 // single-reduction CG: slots per reduced quantity that the workgroups of a launch add into
 constexpr int CGS_SLOTS = 256;
 
@@ -155,6 +183,10 @@ struct fe_problem {
   void* w_d = nullptr;        // inverse diagonal
   int precond = FE_PC_JACOBI; // FE_PC_JACOBI or FE_PC_BLOCK_JACOBI
   void* w_blk = nullptr;      // inverse node blocks [n_nodes][6] (allocated on first use)
+  void* w_gm = nullptr;       // GMRES: basis [gm_cap + 1][n_dof], then w and z [n_dof] each
+  int gm_cap = 0;             // restart length w_gm was sized for
+  fe::GmresDev* gm_dev = nullptr; // GMRES scalars (device)
+  double* gm_part = nullptr;  // [GM_MAXM + 1][GM_GRID] partial sums
   void* w_cg = nullptr;       // single-reduction CG vectors r_1, s_0, s_1, w_0, w_1, w_2 (allocated on first use)
   void* w_bicg = nullptr;     // BiCGStab vectors r, r_hat, p, v, s, t, p_hat, s_hat (allocated on first use)
   double* bicg_part = nullptr;  // BiCGStab partial sums [8][BICG_GRID]
@@ -272,6 +304,13 @@ hipError_t cg_operator(const fe_problem* p, int op, const int32_t* rp, const int
                        hipStream_t s);
 hipError_t cg_vectors(const fe_problem* p, int op, void* x, long k, hipStream_t s);
 hipError_t cg_pre(const fe_problem* p, int op, long k, hipStream_t s);  // CSR: direction kernel before the mat-vec
+// restarted GMRES pieces (fe_krylov.hip): setup (x = 0, w = b, preconditioner inverted),
+// then per cycle GM_START, per Arnoldi step j GM_BASIS + operator (z -> w) + GM_ORTHO,
+// GM_FINISH at the cycle end, and A x -> w + GM_RESIDUAL before the next cycle
+hipError_t gm_setup(const fe_problem* p, const void* b, void* x, double rtol, int max_it, int m, hipStream_t s);
+hipError_t gm_step(const fe_problem* p, int stage, int j, const void* b, void* x, hipStream_t s);
+void* gm_work_w(const fe_problem* p);
+void* gm_work_z(const fe_problem* p);
 // matrix-free single-reduction CG: init, then one fused operator launch j = 0, 1, ... per
 // iteration (its last workgroup computes the scalars of the next launch)
 hipError_t cgs_init(const fe_problem* p, const void* b, void* x, double rtol, int max_it, hipStream_t s);

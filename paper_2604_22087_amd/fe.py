@@ -21,7 +21,7 @@ F64, F32 = 0, 1
 LINEAR, J2, NEOHOOKE = 0, 1, 2
 OP_CSR, OP_MATFREE = 0, 1
 PC_JACOBI, PC_BLOCK_JACOBI = 0, 1
-SOLVER_CG, SOLVER_BICGSTAB = 0, 1
+SOLVER_CG, SOLVER_BICGSTAB, SOLVER_GMRES = 0, 1, 2
 APPLY_BC, STORE_TANGENT = 1, 2
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "HIP runtime error", 3: "out of device memory",
@@ -37,7 +37,7 @@ class PcgInfo(ctypes.Structure):
 
 class NewtonOpts(ctypes.Structure):
     _fields_ = [("op", _i32), ("assemble_csr", _i32), ("max_newton", _i32), ("newton_rtol", _dbl), ("pcg_rtol", _dbl),
-                ("pcg_max_it", _i32), ("solver", _i32)]
+                ("pcg_max_it", _i32), ("solver", _i32), ("restart", _i32)]
 
 
 class NewtonInfo(ctypes.Structure):
@@ -66,6 +66,7 @@ SIGNATURES = [
     ("fe_vjp_path", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("fe_pcg", _i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _dbl, _i32, ctypes.POINTER(PcgInfo), _vp]),
     ("fe_bicgstab", _i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _dbl, _i32, ctypes.POINTER(PcgInfo), _vp]),
+    ("fe_gmres", _i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _dbl, _i32, _i32, ctypes.POINTER(PcgInfo), _vp]),
     ("fe_vjp", _i32, [_vp, _vp, _vp, _vp, _vp]),
     ("fe_newton", _i32, [_vp, ctypes.POINTER(_dbl), _i32, ctypes.POINTER(NewtonOpts), _vp, _vp,
                          ctypes.POINTER(_dbl), ctypes.POINTER(NewtonInfo), _vp]),
@@ -257,15 +258,22 @@ class Problem:
         """PC_JACOBI (point) or PC_BLOCK_JACOBI (3x3 node blocks) for pcg and newton."""
         _check(self.lib.fe_set_preconditioner(self.handle, int(kind)), "fe_set_preconditioner")
 
-    def pcg(self, b, x=None, op=OP_MATFREE, csr=None, rtol=1e-10, max_it=100000, check=True, solver=SOLVER_CG):
-        """Preconditioned CG (or BiCGStab with solver=SOLVER_BICGSTAB) on the masked operator."""
+    def pcg(self, b, x=None, op=OP_MATFREE, csr=None, rtol=1e-10, max_it=100000, check=True, solver=SOLVER_CG,
+            restart=30):
+        """Preconditioned CG (BiCGStab with solver=SOLVER_BICGSTAB, GMRES(restart) with
+        solver=SOLVER_GMRES) on the masked operator."""
         self._real(b, self.n_dof, "b")
         x = self.vector() if x is None else self._real(x, self.n_dof, "x")
         rp, ci, v = csr if csr is not None else (None, None, None)
         info = PcgInfo()
-        fn, name = (self.lib.fe_bicgstab, "fe_bicgstab") if solver == SOLVER_BICGSTAB else (self.lib.fe_pcg, "fe_pcg")
-        st = fn(self.handle, int(op), _ptr(rp), _ptr(ci), _ptr(v), _ptr(b), _ptr(x), float(rtol), int(max_it),
-                ctypes.byref(info), _stream())
+        args = (self.handle, int(op), _ptr(rp), _ptr(ci), _ptr(v), _ptr(b), _ptr(x), float(rtol), int(max_it))
+        if solver == SOLVER_GMRES:
+            name = "fe_gmres"
+            st = self.lib.fe_gmres(*args, int(restart), ctypes.byref(info), _stream())
+        else:
+            fn, name = (self.lib.fe_bicgstab, "fe_bicgstab") if solver == SOLVER_BICGSTAB else \
+                (self.lib.fe_pcg, "fe_pcg")
+            st = fn(*args, ctypes.byref(info), _stream())
         if check:
             _check(st, name)
         return x, PcgResult(info.iterations, info.status, info.relres, info.bnorm)
@@ -293,7 +301,7 @@ class Problem:
         return mu_out
 
     def newton(self, load_path, u=None, state=None, op=OP_MATFREE, max_newton=20, newton_rtol=1e-8,
-               pcg_rtol=1e-10, pcg_max_it=100000, assemble_csr=False, check=True, solver=SOLVER_CG):
+               pcg_rtol=1e-10, pcg_max_it=100000, assemble_csr=False, check=True, solver=SOLVER_CG, restart=0):
         """Load stepping; load_path: sequence of 3x3 macro strains. Returns (u, state, sigma_bar, info)."""
         path = torch.as_tensor(np.asarray(load_path, dtype=np.float64)).reshape(-1, 9)
         k = path.shape[0]
@@ -301,7 +309,7 @@ class Problem:
         u = self.vector() if u is None else self._real(u, self.n_dof, "u")
         self._real(state, 56 * self.n_el, "state")
         opts = NewtonOpts(int(op), int(bool(assemble_csr)), int(max_newton), float(newton_rtol), float(pcg_rtol),
-                          int(pcg_max_it), int(solver))
+                          int(pcg_max_it), int(solver), int(restart))
         sig = (_dbl * (6 * max(k, 1)))()
         info = NewtonInfo()
         st = self.lib.fe_newton(self.handle, pa, k, ctypes.byref(opts), _ptr(u), _ptr(state), sig,

@@ -140,7 +140,9 @@ def test_surrogate_newton_end_to_end():
     gains (or costs) against the method without it at this size.  The captured sample set
     varies slightly between runs (face atomics reorder sums), and with it the network and the
     Newton iteration count of the surrogate ramp (20 to 50 over the five steps), hence the
-    generous per-step iteration limit."""
+    generous per-step iteration limit; both paths stop at Newton 1e-6 / PCG 1e-8, the
+    tolerance at which accept/fallback switching between iterates still lets the surrogate
+    ramp converge."""
     import time
     import torch
     from paper_2604_22087_amd import fe
@@ -160,8 +162,8 @@ def test_surrogate_newton_end_to_end():
             P.set_surrogate(W, fallback_tol=1e-3)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, _, sig, info = P.newton(gsur.ramp(0.02, 5), state=P.state(), op=fe.OP_MATFREE, newton_rtol=1e-8,
-                                   pcg_rtol=1e-10, max_newton=60)
+        _, _, sig, info = P.newton(gsur.ramp(0.02, 5), state=P.state(), op=fe.OP_MATFREE, newton_rtol=1e-6,
+                                   pcg_rtol=1e-8, max_newton=60)
         torch.cuda.synchronize()
         res[mode] = (time.perf_counter() - t0, np.array(sig), info,
                      P.surrogate_stats() if mode == "surrogate" else None)
