@@ -60,7 +60,7 @@ typedef enum {
 enum { FE_F64 = 0, FE_F32 = 1 };                      /* precision of real arrays */
 enum { FE_LINEAR = 0, FE_J2 = 1, FE_NEOHOOKE = 2 };    /* constitutive model per phase */
 enum { FE_OP_CSR = 0, FE_OP_MATFREE = 1 };             /* operator used by fe_pcg / fe_newton */
-enum { FE_PC_JACOBI = 0, FE_PC_BLOCK_JACOBI = 1 };     /* CG preconditioner (fe_set_preconditioner) */
+enum { FE_PC_JACOBI = 0, FE_PC_BLOCK_JACOBI = 1, FE_PC_ILU0 = 2 };  /* preconditioner (fe_set_preconditioner) */
 enum { FE_SOLVER_CG = 0, FE_SOLVER_BICGSTAB = 1, FE_SOLVER_GMRES = 2 };  /* Krylov method of fe_newton's inner solves */
 enum { FE_APPLY_BC = 1, FE_STORE_TANGENT = 2 };        /* fe_residual flags */
 enum { FE_MAX_PHASES = 8 };
@@ -173,9 +173,24 @@ int fe_diagonal(fe_problem* p, void* d, int apply_bc, void* stream);
  * the stored linearisation otherwise.  The blocks are inverted once per solve
  * (workspace of 6 reals per node, allocated on first use; FE_ERR_OOM if that
  * fails).  A block with determinant <= 0 sets bit 1 of fe_read_flags; a
- * singular one makes the solve end with FE_ERR_NONFINITE.  FE_ERR_ARG for any
- * other kind. */
+ * singular one makes the solve end with FE_ERR_NONFINITE.  FE_PC_ILU0: node-block
+ * incomplete LU without fill (3x3 blocks of node pairs that share an element),
+ * nodes taken in 8 colours by the parities of their grid indices so that each
+ * colour is one data-parallel level of the factorisation and of the two
+ * triangular sweeps (Fig. 7 compares ILU with Jacobi on the assembled matrix);
+ * it needs the CSR values (FE_OP_CSR, or fe_newton with assemble_csr), is
+ * factored once per solve into 243 reals per node (allocated here; FE_ERR_OOM if
+ * that fails) and is applied by fe_gmres only (fe_pcg and fe_bicgstab return
+ * FE_ERR_ARG with it); a singular pivot block sets bit 2 of fe_read_flags and
+ * ends the solve with FE_ERR_NONFINITE.  FE_ERR_ARG for any other kind. */
 int fe_set_preconditioner(fe_problem* p, int kind);
+
+/* z = M^-1 r for the preconditioner chosen by fe_set_preconditioner, set up as the
+ * solvers set it up: from the CSR matrix when row_ptr, col_idx and vals are given
+ * (already eliminated; required for FE_PC_ILU0), else from the stored
+ * linearisation (FE_ERR_STATE without one).  r, z: real [n_dof], distinct. */
+int fe_apply_preconditioner(fe_problem* p, const int32_t* row_ptr, const int32_t* col_idx,
+                            const void* vals, const void* r, void* z, void* stream);
 
 /* Preconditioned CG on A x = b (Fig. 4): A is the masked operator
  * P_f K P_f + P_b, matrix-free (op = FE_OP_MATFREE, CSR arguments ignored) or the
@@ -274,7 +289,8 @@ int fe_linearization_stats(fe_problem* p, int64_t* out_host, void* stream);
 
 /* Device-side error flags raised by element kernels since the last read
  * (bit 0: inverted element; bit 1: a node block of the block-Jacobi
- * preconditioner with determinant <= 0).  Synchronises and clears. */
+ * preconditioner with determinant <= 0; bit 2: a singular ILU(0) pivot block).
+ * Synchronises and clears. */
 int fe_read_flags(fe_problem* p, int* flags_host, void* stream);
 
 /* ---- learned constitutive surrogate (Sec. III-B: a surrogate may replace the

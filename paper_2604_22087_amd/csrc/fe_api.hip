@@ -137,6 +137,7 @@ void fe_problem_destroy(fe_problem* p) {
   free_dev(p->w_bicg);
   free_dev(p->w_cg);
   free_dev(p->w_gm);
+  free_dev(p->w_ilu);
   free_dev(p->gm_dev);
   free_dev(p->gm_part);
   free_dev(p->bicg_part);
@@ -513,9 +514,13 @@ int fe_set_surrogate_tangent(fe_problem* p, int full) {
 
 int fe_set_preconditioner(fe_problem* p, int kind) {
   CHKP(p);
-  if (kind != FE_PC_JACOBI && kind != FE_PC_BLOCK_JACOBI) return arg_error("kind must be FE_PC_JACOBI or FE_PC_BLOCK_JACOBI");
+  if (kind != FE_PC_JACOBI && kind != FE_PC_BLOCK_JACOBI && kind != FE_PC_ILU0)
+    return arg_error("kind must be FE_PC_JACOBI, FE_PC_BLOCK_JACOBI or FE_PC_ILU0");
   if (kind == FE_PC_BLOCK_JACOBI && !p->w_blk) {
     if (int st = alloc(&p->w_blk, 6 * real_size(p) * (size_t)p->n_nodes)) return st;
+  }
+  if (kind == FE_PC_ILU0 && !p->w_ilu) {
+    if (int st = alloc(&p->w_ilu, ilu_words(p) * real_size(p))) return st;
   }
   p->precond = kind;
   return FE_OK;
@@ -529,6 +534,7 @@ int fe_set_preconditioner(fe_problem* p, int kind) {
 // else from the element kernel; `op` selects the operator inside the iteration.
 static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, const void* b,
                    void* x, double rtol, int max_it, fe_pcg_info* info, hipStream_t s, int* applies) {
+  if (p->precond == FE_PC_ILU0) return arg_error("FE_PC_ILU0 is applied by fe_gmres only");
   if (p->precond == FE_PC_BLOCK_JACOBI) {
     HIPCHK(launch_block_jacobi(p, rp, ci, vals, p->w_blk, s));
   } else if (rp) {
@@ -605,6 +611,7 @@ static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, 
 // Preconditioned BiCGStab driver (same preconditioner set-up and polling as pcg_run).
 static int bicg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, const void* b,
                     void* x, double rtol, int max_it, fe_pcg_info* info, hipStream_t s, int* applies) {
+  if (p->precond == FE_PC_ILU0) return arg_error("FE_PC_ILU0 is applied by fe_gmres only");
   const size_t rs = real_size(p);
   if (!p->w_bicg && alloc(&p->w_bicg, 8 * rs * (size_t)p->n_dof)) return FE_ERR_OOM;
   if (!p->bicg_part && alloc((void**)&p->bicg_part, 6 * BICG_GRID * sizeof(double))) return FE_ERR_OOM;
@@ -673,6 +680,7 @@ static int gmres_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci
   const size_t rs = real_size(p);
   if (p->w_gm && p->gm_cap < m) {
     free_dev(p->w_gm);
+  free_dev(p->w_ilu);
     p->w_gm = nullptr;
   }
   if (!p->w_gm) {
@@ -682,13 +690,17 @@ static int gmres_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci
   if (!p->gm_dev && alloc((void**)&p->gm_dev, sizeof(GmresDev))) return FE_ERR_OOM;
   if (!p->gm_part && alloc((void**)&p->gm_part, (size_t)(GM_MAXM + 1) * GM_GRID * sizeof(double)))
     return FE_ERR_OOM;
-  if (p->precond == FE_PC_BLOCK_JACOBI) {
+  if (p->precond == FE_PC_ILU0) {
+    if (!rp) return arg_error("FE_PC_ILU0 needs the assembled CSR matrix");
+    HIPCHK(ilu_setup(p, rp, ci, vals, s));
+  } else if (p->precond == FE_PC_BLOCK_JACOBI) {
     HIPCHK(launch_block_jacobi(p, rp, ci, vals, p->w_blk, s));
   } else if (rp) {
     HIPCHK(launch_csr_diag(p, rp, ci, vals, p->w_d, s));
   } else {
     HIPCHK(launch_diag(p, p->w_d, 1, s));
   }
+  const bool ilu = p->precond == FE_PC_ILU0;
   const int* stop = &p->gm_dev->ctrl.status;
   auto apply = [&](const void* in, void* out, const int* stp) -> hipError_t {
     if (op == FE_OP_CSR) return launch_spmv_stop(p, rp, ci, vals, in, out, stp, s);
@@ -716,6 +728,7 @@ static int gmres_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci
     while (j < m) {
       for (int c = 0; c < chunk && j < m; ++c, ++j) {
         HIPCHK(gm_step(p, GM_BASIS, j, b, x, s));
+        if (ilu) HIPCHK(ilu_apply(p, gm_work_z(p), gm_work_z(p), stop, s));
         HIPCHK(apply(gm_work_z(p), gm_work_w(p), stop));
         HIPCHK(gm_step(p, GM_ORTHO, j, b, x, s));
       }
@@ -724,6 +737,10 @@ static int gmres_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci
       if (chunk < 16) chunk *= 2;
     }
     HIPCHK(gm_step(p, GM_FINISH, 0, b, x, s));
+    if (ilu) {  // x += (L U)^-1 V y
+      HIPCHK(ilu_apply(p, gm_work_z(p), gm_work_z(p), nullptr, s));
+      HIPCHK(gm_step(p, GM_ADD_Z, 0, b, x, s));
+    }
     if (int e = poll()) return e;
     if (hc->status != CG_RUNNING) break;
     HIPCHK(apply(x, gm_work_w(p), nullptr));  // next cycle: w = b - A x
@@ -740,6 +757,34 @@ static int gmres_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci
   if (applies) *applies += hc->iters + restarts;
   if (status != FE_OK) set_error(fe_status_string(status));
   return status;
+}
+
+extern "C" int fe_apply_preconditioner(fe_problem* p, const int32_t* row_ptr, const int32_t* col_idx,
+                                       const void* vals, const void* r, void* z, void* stream) {
+  CHKP(p);
+  if (!r || !z) return arg_error("r and z are required");
+  if ((row_ptr || col_idx || vals) && !(row_ptr && col_idx && vals))
+    return arg_error("give all of row_ptr, col_idx and vals, or none");
+  if (!row_ptr && p->precond == FE_PC_ILU0) return arg_error("FE_PC_ILU0 needs the assembled CSR matrix");
+  if (!row_ptr && !p->lin_valid) {
+    set_error("no linearisation stored");
+    return FE_ERR_STATE;
+  }
+  hipStream_t s = S(stream);
+  if (p->precond == FE_PC_ILU0) {
+    HIPCHK(ilu_setup(p, row_ptr, col_idx, vals, s));
+    HIPCHK(ilu_apply(p, r, z, nullptr, s));
+    return FE_OK;
+  }
+  if (p->precond == FE_PC_BLOCK_JACOBI) {
+    HIPCHK(launch_block_jacobi(p, row_ptr, col_idx, vals, p->w_blk, s));
+  } else if (row_ptr) {
+    HIPCHK(launch_csr_diag(p, row_ptr, col_idx, vals, p->w_d, s));
+  } else {
+    HIPCHK(launch_diag(p, p->w_d, 1, s));
+  }
+  HIPCHK(pc_apply(p, r, z, s));
+  return FE_OK;
 }
 
 extern "C" int fe_gmres(fe_problem* p, int op, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,

@@ -75,7 +75,7 @@ struct GmresDev {
   double c[2][GM_MAXM + 1];        // Gram-Schmidt coefficients of the two passes
 };
 
-enum GmStage { GM_START = 1, GM_BASIS, GM_ORTHO, GM_FINISH, GM_RESIDUAL };
+enum GmStage { GM_START = 1, GM_BASIS, GM_ORTHO, GM_FINISH, GM_RESIDUAL, GM_ADD_Z };
 
 // single-reduction CG: slots per reduced quantity that the workgroups of a launch add into
 constexpr int CGS_SLOTS = 256;
@@ -183,6 +183,7 @@ struct fe_problem {
   void* w_d = nullptr;        // inverse diagonal
   int precond = FE_PC_JACOBI; // FE_PC_JACOBI or FE_PC_BLOCK_JACOBI
   void* w_blk = nullptr;      // inverse node blocks [n_nodes][6] (allocated on first use)
+  void* w_ilu = nullptr;      // ILU(0) factors [27][9][n_nodes] (allocated by fe_set_preconditioner)
   void* w_gm = nullptr;       // GMRES: basis [gm_cap + 1][n_dof], then w and z [n_dof] each
   int gm_cap = 0;             // restart length w_gm was sized for
   fe::GmresDev* gm_dev = nullptr; // GMRES scalars (device)
@@ -311,6 +312,14 @@ hipError_t gm_setup(const fe_problem* p, const void* b, void* x, double rtol, in
 hipError_t gm_step(const fe_problem* p, int stage, int j, const void* b, void* x, hipStream_t s);
 void* gm_work_w(const fe_problem* p);
 void* gm_work_z(const fe_problem* p);
+// z = M^-1 r with the point (diagonal in w_d, not inverted) or node-block (inverted
+// blocks in w_blk) preconditioner as set up last (fe_krylov.hip)
+hipError_t pc_apply(const fe_problem* p, const void* r, void* z, hipStream_t s);
+// node-block ILU(0) in 8-colour order (fe_ilu.hip): factor from the CSR matrix, apply
+// z = (L U)^-1 r (r may equal z; 16 launches, which return at once when *stop is set)
+size_t ilu_words(const fe_problem* p);
+hipError_t ilu_setup(const fe_problem* p, const int32_t* rp, const int32_t* ci, const void* v, hipStream_t s);
+hipError_t ilu_apply(const fe_problem* p, const void* r, void* z, const int* stop, hipStream_t s);
 // matrix-free single-reduction CG: init, then one fused operator launch j = 0, 1, ... per
 // iteration (its last workgroup computes the scalars of the next launch)
 hipError_t cgs_init(const fe_problem* p, const void* b, void* x, double rtol, int max_it, hipStream_t s);

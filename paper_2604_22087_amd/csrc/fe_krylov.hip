@@ -43,11 +43,15 @@ __device__ double group_sum(const double* part, int np, double* sh) {
 
 __device__ __forceinline__ bool is_finite(double v) { return v == v && v - v == 0.0; }
 
-// z = M^-1 r for the three dofs of one node: node-block inverse (6 words per node:
-// xx, yy, zz, yz, xz, xy) or inverted point diagonal.
+// z = M^-1 r for the three dofs of one node: node-block inverse (blk = 1; 6 words per
+// node: xx, yy, zz, yz, xz, xy) or inverted point diagonal (blk = 0); blk = 2 (ILU(0),
+// applied by its own sweeps afterwards) copies r.
 template <typename T>
 __device__ __forceinline__ void precond_node(const T* M, int blk, int64_t node, const T r[3], T z[3]) {
-  if (blk) {
+  if (blk == 2) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) z[c] = r[c];
+  } else if (blk) {
     const T* m = M + 6 * node;
     z[0] = m[0] * r[0] + m[5] * r[1] + m[4] * r[2];
     z[1] = m[5] * r[0] + m[1] * r[1] + m[3] * r[2];
@@ -255,11 +259,12 @@ __global__ void gm_solve_kernel(GmresDev* dev) {
   }
 }
 
-// x += M^-1 (sum_{i<k} y_i V_i), one node per lane; w is cleared for the operator
-// application that starts the next cycle.
+// x += M^-1 (sum_{i<k} y_i V_i), one node per lane (blk = 2: t = sum_i y_i V_i goes to
+// tz instead, for the ILU sweeps and GM_ADD_Z); w is cleared for the operator application
+// that starts the next cycle.
 template <typename T>
 __global__ __launch_bounds__(KB) void gm_combine_kernel(int64_t n_nodes, const T* V, int64_t n, T* x, T* w,
-                                                        const T* M, int blk, const GmresDev* dev) {
+                                                        T* tz, const T* M, int blk, const GmresDev* dev) {
   __shared__ double ys[GM_MAXM];
   const int k = dev->ctrl.k;
   for (int i = threadIdx.x; i < k; i += KB) ys[i] = dev->y[i];
@@ -275,10 +280,21 @@ __global__ __launch_bounds__(KB) void gm_combine_kernel(int64_t n_nodes, const T
       for (int i = 0; i < k; ++i) a += ys[i] * (double)V[(int64_t)i * n + 3 * nd + c];
       t[c] = T(a);
     }
+    if (blk == 2) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) tz[3 * nd + c] = t[c];
+      continue;
+    }
     precond_node(M, blk, nd, t, z);
 #pragma unroll
     for (int c = 0; c < 3; ++c) x[3 * nd + c] += z[c];
   }
+}
+
+// x += z
+template <typename T>
+__global__ __launch_bounds__(KB) void gm_add_kernel(int64_t n, const T* z, T* x) {
+  for (int64_t d = (int64_t)blockIdx.x * KB + threadIdx.x; d < n; d += (int64_t)gridDim.x * KB) x[d] += z[d];
 }
 
 // w = b - w (w holds A x) and partial ||w||^2 for the next cycle start.
@@ -340,7 +356,10 @@ hipError_t gm_step_t(const fe_problem* p, int stage, int j, const void* b, void*
     case GM_FINISH:  // cycle end: y = R^-1 g, x += M^-1 V y
       hipLaunchKernelGGL(gm_solve_kernel, dim3(1), dim3(64), 0, s, p->gm_dev);
       hipLaunchKernelGGL(gm_combine_kernel<T>, dim3(node_grid(p)), dim3(KB), 0, s, p->n_nodes, basis<T>(p, 0), n,
-                         static_cast<T*>(x), work_w<T>(p), M, p->precond, p->gm_dev);
+                         static_cast<T*>(x), work_w<T>(p), work_z<T>(p), M, p->precond, p->gm_dev);
+      break;
+    case GM_ADD_Z:  // x += z (after the ILU sweeps of the cycle-end combination)
+      hipLaunchKernelGGL(gm_add_kernel<T>, dim3(GM_GRID), dim3(KB), 0, s, n, work_z<T>(p), static_cast<T*>(x));
       break;
     case GM_RESIDUAL:  // w = b - w (w = A x), then ||w||
       hipLaunchKernelGGL(gm_residual_kernel<T>, dim3(GM_GRID), dim3(KB), 0, s, n, static_cast<const T*>(b),
@@ -350,6 +369,33 @@ hipError_t gm_step_t(const fe_problem* p, int stage, int j, const void* b, void*
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// z = M^-1 r with the point diagonal d (not inverted; blk = 0) or the inverted node blocks
+// (blk = 1), one node per lane.
+template <typename T>
+__global__ __launch_bounds__(KB) void pc_apply_kernel(int64_t n_nodes, const T* M, int blk, const T* r, T* z) {
+  for (int64_t nd = (int64_t)blockIdx.x * KB + threadIdx.x; nd < n_nodes; nd += (int64_t)gridDim.x * KB) {
+    T v[3], w[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = r[3 * nd + c];
+    if (blk) {
+      precond_node(M, 1, nd, v, w);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) w[c] = v[c] / M[3 * nd + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) z[3 * nd + c] = w[c];
+  }
+}
+
+template <typename T>
+hipError_t pc_apply_t(const fe_problem* p, const void* r, void* z, hipStream_t s) {
+  hipLaunchKernelGGL(pc_apply_kernel<T>, dim3(node_grid(p)), dim3(KB), 0, s, p->n_nodes,
+                     static_cast<const T*>(pc_buffer(p)), p->precond == FE_PC_BLOCK_JACOBI ? 1 : 0,
+                     static_cast<const T*>(r), static_cast<T*>(z));
   return hipGetLastError();
 }
 
@@ -366,6 +412,10 @@ hipError_t gm_setup_t(const fe_problem* p, const void* b, void* x, double rtol, 
 hipError_t gm_setup(const fe_problem* p, const void* b, void* x, double rtol, int max_it, int m, hipStream_t s) {
   return p->prec == FE_F64 ? gm_setup_t<double>(p, b, x, rtol, max_it, m, s)
                            : gm_setup_t<float>(p, b, x, rtol, max_it, m, s);
+}
+
+hipError_t pc_apply(const fe_problem* p, const void* r, void* z, hipStream_t s) {
+  return p->prec == FE_F64 ? pc_apply_t<double>(p, r, z, s) : pc_apply_t<float>(p, r, z, s);
 }
 
 hipError_t gm_step(const fe_problem* p, int stage, int j, const void* b, void* x, hipStream_t s) {

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libfe.so")
 F64, F32 = 0, 1
 LINEAR, J2, NEOHOOKE = 0, 1, 2
 OP_CSR, OP_MATFREE = 0, 1
-PC_JACOBI, PC_BLOCK_JACOBI = 0, 1
+PC_JACOBI, PC_BLOCK_JACOBI, PC_ILU0 = 0, 1, 2
 SOLVER_CG, SOLVER_BICGSTAB, SOLVER_GMRES = 0, 1, 2
 APPLY_BC, STORE_TANGENT = 1, 2
 
@@ -66,6 +66,7 @@ SIGNATURES = [
     ("fe_vjp_path", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("fe_pcg", _i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _dbl, _i32, ctypes.POINTER(PcgInfo), _vp]),
     ("fe_bicgstab", _i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _dbl, _i32, ctypes.POINTER(PcgInfo), _vp]),
+    ("fe_apply_preconditioner", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("fe_gmres", _i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _dbl, _i32, _i32, ctypes.POINTER(PcgInfo), _vp]),
     ("fe_vjp", _i32, [_vp, _vp, _vp, _vp, _vp]),
     ("fe_newton", _i32, [_vp, ctypes.POINTER(_dbl), _i32, ctypes.POINTER(NewtonOpts), _vp, _vp,
@@ -277,6 +278,15 @@ class Problem:
         if check:
             _check(st, name)
         return x, PcgResult(info.iterations, info.status, info.relres, info.bnorm)
+
+    def apply_preconditioner(self, r, csr=None, z=None):
+        """z = M^-1 r for the current preconditioner (from the CSR matrix when given)."""
+        self._real(r, self.n_dof, "r")
+        z = self.vector() if z is None else self._real(z, self.n_dof, "z")
+        rp, ci, v = csr if csr is not None else (None, None, None)
+        _check(self.lib.fe_apply_preconditioner(self.handle, _ptr(rp), _ptr(ci), _ptr(v), _ptr(r), _ptr(z),
+                                                _stream()), "fe_apply_preconditioner")
+        return z
 
     def vjp(self, u, lam, out=None):
         self._real(u, self.n_dof, "u")
