@@ -244,10 +244,54 @@ def adjoint_path_leg(n):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     g = s.grad.double()
-    return {"workload": f"{n}^3 fiber RVE, 3-step non-proportional path, dJ/ds for {n ** 3} elements",
-            "J": float(J.detach()), "forward_seconds": t1 - t0, "backward_seconds": t2 - t1,
-            "grad_norm": float(torch.linalg.norm(g)), "grad_min": float(g.min()), "grad_max": float(g.max()),
-            "checkpoint_bytes": 3 * (56 * P.n_el + P.n_dof) * 8}
+    out = {"workload": f"{n}^3 fiber RVE, 3-step non-proportional path, dJ/ds for {n ** 3} elements",
+           "J": float(J.detach()), "forward_seconds": t1 - t0, "backward_seconds": t2 - t1,
+           "grad_norm": float(torch.linalg.norm(g)), "grad_min": float(g.min()), "grad_max": float(g.max()),
+           "checkpoint_bytes": 3 * (56 * P.n_el + P.n_dof) * 8}
+    # the same gradient keeping one state besides the initial one (binomial schedule)
+    s1 = s.detach().clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J1 = ReactionWorkPath.apply(s1, P, torch.tensor(phase, device="cuda"), [fe.J2, fe.LINEAR],
+                                [MATRIX, FIBER + (0.0, 0.0)], torch.tensor(inputs.boundary_dof_mask(n), device="cuda"),
+                                path, 1e-10, 1e-12, 1)
+    J1.backward()
+    torch.cuda.synchronize()
+    out["one_checkpoint"] = {"seconds": time.perf_counter() - t0, "rerun_load_steps": J1.grad_fn.recompute_solves,
+                             "checkpoint_bytes": 2 * (56 * P.n_el + P.n_dof) * 8,
+                             "max_rel_grad_diff": float((s1.grad.double() - g).abs().max() / g.abs().max())}
+    return out
+
+
+def inverse_leg(n):
+    """Material-parameter inverse problem on the n^3 fiber RVE: the modulus scales of the J2
+    matrix and the fibers (1.3, 0.7) behind the reaction work of a 3-step tension path and a
+    3-step shear path are recovered from (1, 1) by Gauss-Newton with path-adjoint gradients
+    (one checkpoint besides the initial state)."""
+    import torch
+    from paper_2604_22087_amd import fe, inputs
+    from paper_2604_22087_amd.adjoint import fit_phase_scales, reaction_work_path
+
+    def strain(xx, xy):
+        return np.array([[xx, xy, 0.0], [xy, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    paths = [[strain(0.004 * k, 0.0) for k in (1, 2, 3)], [strain(0.0, 0.004 * k) for k in (1, 2, 3)]]
+    phase = torch.tensor(inputs.fiber_phase(n, n_fibers=64, radius=0.05, seed=2), device="cuda")
+    mask = torch.tensor(inputs.boundary_dof_mask(n), device="cuda")
+    models, params = [fe.J2, fe.LINEAR], [MATRIX, FIBER + (0.0, 0.0)]
+    true = np.array([1.3, 0.7])
+    P = fe.Problem(n, "f64")
+    targets = [float(reaction_work_path(torch.tensor(true, device="cuda")[phase.long()], P, phase, models, params,
+                                        mask, path, 1e-10, 1e-12)) for path in paths]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    theta, hist = fit_phase_scales(P, phase, models, params, mask, paths, targets, [1.0, 1.0], newton_rtol=1e-10,
+                                   pcg_rtol=1e-12, checkpoints=1,
+                                   log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+    torch.cuda.synchronize()
+    return {"workload": f"{n}^3 fiber RVE, phase modulus scales from the reaction work of a tension and a shear "
+                        f"path (3 steps each)", "true": true.tolist(), "fitted": theta.tolist(),
+            "max_abs_error": float(np.abs(theta - true).max()), "gauss_newton_iterations": len(hist),
+            "seconds": time.perf_counter() - t0, "history": hist}
 
 
 def csr_scaling_leg(sizes):
@@ -310,6 +354,7 @@ def main():
     ap.add_argument("--nh", type=int, default=0, help="also run the finite-strain Neo-Hookean leg at this n (0: skip)")
     ap.add_argument("--surrogate", type=int, default=96, help="n of the surrogate-vs-return-map leg (0: skip)")
     ap.add_argument("--adjoint-path", type=int, default=64, help="n of the plastic-path adjoint leg (0: skip)")
+    ap.add_argument("--inverse", type=int, default=0, help="n of the inverse-problem leg (0: skip)")
     ap.add_argument("--csr-sizes", default="96,128", help="mesh sizes of the assembled-operator leg ('' to skip)")
     ap.add_argument("--copy-calib", action="store_true", help="run only a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -413,6 +458,9 @@ def main():
     if args.adjoint_path:
         print(f"[bench] adjoint path leg {args.adjoint_path}^3", file=sys.stderr, flush=True)
         out["adjoint_path"] = adjoint_path_leg(args.adjoint_path)
+    if args.inverse:
+        print(f"[bench] inverse-problem leg {args.inverse}^3", file=sys.stderr, flush=True)
+        out["inverse"] = inverse_leg(args.inverse)
     if args.nh:
         print(f"[bench] neo-hookean leg {args.nh}^3", file=sys.stderr, flush=True)
         out["neohooke"] = neohooke_leg(args.nh)

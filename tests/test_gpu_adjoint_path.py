@@ -86,3 +86,57 @@ def test_path_gradient_finite_differences_fiber():
         errs.append(abs((jp - jm) / (2 * h) - g[e]) / abs(g[e]))
     print(f"  FD vs adjoint: {np.array(errs)}", flush=True)
     assert max(errs) <= 1e-6
+
+
+PATH5 = [_strain(0.006, 0.0), _strain(0.012, 0.0), _strain(0.012, 0.006), _strain(0.008, 0.010),
+         _strain(0.004, 0.012)]
+
+
+def test_path_gradient_binomial_checkpoints_match_store_all():
+    """Keeping only c + 1 states and re-running steps (binomial schedule) gives the gradient
+    of the store-all sweep, with the predicted number of re-run load steps."""
+    from paper_2604_22087_amd import fe
+    from paper_2604_22087_amd.adjoint import revolve_cost
+    n = 8
+    print("[adjoint path] n=8 binomial checkpoints", flush=True)
+    phase = inputs.fiber_phase(n, n_fibers=4, radius=0.18, seed=2)
+    s = inputs.uniform_field(n ** 3, 0.8, 1.2, seed=6)
+    models, params = [fe.J2, fe.LINEAR], [J2P, (230.0, 0.2, 0.0, 0.0)]
+    J0, g0, _ = _gpu(n, phase, s, models, params, PATH5)
+    for c in (0, 1, 2):
+        import torch
+        from paper_2604_22087_amd.adjoint import reaction_work_path
+        P = fe.Problem(n, "f64")
+        st = torch.tensor(s, device="cuda", requires_grad=True)
+        J = reaction_work_path(st, P, torch.tensor(phase, dtype=torch.uint8, device="cuda"), models, params,
+                               torch.tensor(inputs.boundary_dof_mask(n), device="cuda"), PATH5, checkpoints=c)
+        J.backward()
+        solves = J.grad_fn.recompute_solves
+        print(f"  checkpoints {c}: {solves} re-run load steps", flush=True)
+        assert solves == revolve_cost(len(PATH5), c)
+        assert float(J) == pytest.approx(J0, rel=1e-12)
+        assert rel_err(st.grad.cpu().numpy(), g0) <= 1e-9
+
+
+def test_inverse_fit_recovers_phase_scales():
+    """Gauss-Newton on the reaction work of a tension and a shear path recovers the two
+    phase modulus scales that produced the targets."""
+    import torch
+    from paper_2604_22087_amd import fe
+    from paper_2604_22087_amd.adjoint import fit_phase_scales, reaction_work_path
+    n = 8
+    print("[adjoint path] n=8 inverse fit", flush=True)
+    phase = torch.tensor(inputs.fiber_phase(n, n_fibers=4, radius=0.18, seed=2), dtype=torch.uint8, device="cuda")
+    mask = torch.tensor(inputs.boundary_dof_mask(n), device="cuda")
+    models, params = [fe.J2, fe.LINEAR], [J2P, (230.0, 0.2, 0.0, 0.0)]
+    paths = [[_strain(0.006, 0.0), _strain(0.012, 0.0)], [_strain(0.0, 0.006), _strain(0.0, 0.012)]]
+    true = np.array([1.3, 0.7])
+    P = fe.Problem(n, "f64")
+    targets = []
+    for path in paths:
+        s = torch.tensor(true, device="cuda")[phase.long()]
+        targets.append(float(reaction_work_path(s, P, phase, models, params, mask, path)))
+    theta, hist = fit_phase_scales(P, phase, models, params, mask, paths, targets, [1.0, 1.0], checkpoints=1,
+                                   log=lambda m: print("  " + m, flush=True))
+    assert np.abs(theta - true).max() <= 1e-6
+    assert len(hist) <= 8
