@@ -138,6 +138,8 @@ void fe_problem_destroy(fe_problem* p) {
   free_dev(p->w_cg);
   free_dev(p->w_gm);
   free_dev(p->w_ilu);
+  free_dev(p->w_ipcg);
+  free_dev(p->ipcg);
   free_dev(p->gm_dev);
   free_dev(p->gm_part);
   free_dev(p->bicg_part);
@@ -532,9 +534,68 @@ int fe_set_preconditioner(fe_problem* p, int kind) {
 // word every `chunk` iterations (iterations after convergence are no-ops).
 // The Jacobi diagonal comes from the CSR matrix when one is given (rp != null),
 // else from the element kernel; `op` selects the operator inside the iteration.
+// CG with the ILU(0) preconditioner (applied by its own sweeps, so not fused into the
+// operator launch): per iteration q = A p, step, test, z = (L U)^-1 r, new direction.
+static int ipcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, const void* b,
+                    void* x, double rtol, int max_it, fe_pcg_info* info, hipStream_t s, int* applies) {
+  if (!rp) return arg_error("FE_PC_ILU0 needs the assembled CSR matrix");
+  if (!p->w_ipcg && alloc(&p->w_ipcg, 4 * real_size(p) * (size_t)p->n_dof)) return FE_ERR_OOM;
+  if (!p->ipcg && alloc((void**)&p->ipcg, sizeof(IpcgCtrl))) return FE_ERR_OOM;
+  if (!p->gm_part && alloc((void**)&p->gm_part, (size_t)(GM_MAXM + 1) * GM_GRID * sizeof(double)))
+    return FE_ERR_OOM;
+  HIPCHK(ilu_setup(p, rp, ci, vals, s));
+  const int* stop = &p->ipcg->status;
+  void* r = ipcg_vec(p, 0);
+  void* pv = ipcg_vec(p, 1);
+  void* q = ipcg_vec(p, 2);
+  void* z = ipcg_vec(p, 3);
+  auto apply = [&]() -> hipError_t {
+    if (op == FE_OP_CSR) return launch_spmv_stop(p, rp, ci, vals, pv, q, stop, s);
+    ElemArgs a = base_args(p);
+    a.x = pv;
+    a.xlin = p->u_lin;
+    a.y = q;
+    a.apply_bc = 1;
+    return launch_elem_stop(p, OP_APPLY, a, stop, s);
+  };
+  HIPCHK(ipcg_step(p, IPCG_INIT, 0, b, x, rtol, max_it, s));
+  HIPCHK(ipcg_step(p, IPCG_CHECK_FIRST, 0, b, x, rtol, max_it, s));
+  HIPCHK(ilu_apply(p, r, z, stop, s));
+  HIPCHK(ipcg_step(p, IPCG_FIRST_DIRECTION, 0, b, x, rtol, max_it, s));
+  IpcgCtrl* hc = reinterpret_cast<IpcgCtrl*>(p->host_buf);
+  static_assert(sizeof(IpcgCtrl) <= 64 * sizeof(double), "host scratch too small");
+  int launched = 0, chunk = 4;
+  long k = 0;
+  for (;;) {
+    HIPCHK(hipMemcpyAsync(hc, p->ipcg, sizeof(IpcgCtrl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hc->status != CG_RUNNING || launched > max_it + 16) break;
+    for (int c = 0; c < chunk; ++c, ++k) {
+      HIPCHK(apply());
+      HIPCHK(ipcg_step(p, IPCG_UPDATE, k, b, x, rtol, max_it, s));
+      HIPCHK(ipcg_step(p, IPCG_CHECK, k, b, x, rtol, max_it, s));
+      HIPCHK(ilu_apply(p, r, z, stop, s));
+      HIPCHK(ipcg_step(p, IPCG_DIRECTION, k + 1, b, x, rtol, max_it, s));
+    }
+    launched += chunk;
+    if (chunk < 16) chunk *= 2;
+  }
+  const int status = hc->status == CG_RUNNING ? FE_ERR_NOT_CONVERGED
+                     : (hc->status == CG_CONVERGED ? FE_OK : hc->status);
+  if (info) {
+    info->iterations = hc->iters;
+    info->status = status;
+    info->bnorm = std::sqrt(hc->bb);
+    info->relres = hc->bb > 0 ? std::sqrt(hc->rr / hc->bb) : 0.0;
+  }
+  if (applies) *applies += hc->iters + (status == FE_ERR_BREAKDOWN || status == FE_ERR_NONFINITE ? 1 : 0);
+  if (status != FE_OK) set_error(fe_status_string(status));
+  return status;
+}
+
 static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, const void* b,
                    void* x, double rtol, int max_it, fe_pcg_info* info, hipStream_t s, int* applies) {
-  if (p->precond == FE_PC_ILU0) return arg_error("FE_PC_ILU0 is applied by fe_gmres only");
+  if (p->precond == FE_PC_ILU0) return ipcg_run(p, op, rp, ci, vals, b, x, rtol, max_it, info, s, applies);
   if (p->precond == FE_PC_BLOCK_JACOBI) {
     HIPCHK(launch_block_jacobi(p, rp, ci, vals, p->w_blk, s));
   } else if (rp) {
@@ -611,7 +672,7 @@ static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, 
 // Preconditioned BiCGStab driver (same preconditioner set-up and polling as pcg_run).
 static int bicg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, const void* b,
                     void* x, double rtol, int max_it, fe_pcg_info* info, hipStream_t s, int* applies) {
-  if (p->precond == FE_PC_ILU0) return arg_error("FE_PC_ILU0 is applied by fe_gmres only");
+  if (p->precond == FE_PC_ILU0) return arg_error("FE_PC_ILU0 is applied by fe_gmres and fe_pcg only");
   const size_t rs = real_size(p);
   if (!p->w_bicg && alloc(&p->w_bicg, 8 * rs * (size_t)p->n_dof)) return FE_ERR_OOM;
   if (!p->bicg_part && alloc((void**)&p->bicg_part, 6 * BICG_GRID * sizeof(double))) return FE_ERR_OOM;
@@ -681,6 +742,8 @@ static int gmres_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci
   if (p->w_gm && p->gm_cap < m) {
     free_dev(p->w_gm);
   free_dev(p->w_ilu);
+  free_dev(p->w_ipcg);
+  free_dev(p->ipcg);
     p->w_gm = nullptr;
   }
   if (!p->w_gm) {

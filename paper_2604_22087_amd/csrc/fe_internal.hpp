@@ -75,6 +75,16 @@ struct GmresDev {
   double c[2][GM_MAXM + 1];        // Gram-Schmidt coefficients of the two passes
 };
 
+// CG with a separately applied preconditioner (ILU(0)), fe_krylov.hip
+struct IpcgCtrl {
+  double rzs[2];     // (r_k, z_k) of iteration k in slot k & 1
+  double alpha, pq;  // last step length and (p, A p)
+  double rtol, bb, tol2, rr;
+  int status, iters, max_it, pad;
+};
+
+enum IpcgStage { IPCG_INIT = 1, IPCG_CHECK_FIRST, IPCG_FIRST_DIRECTION, IPCG_UPDATE, IPCG_CHECK, IPCG_DIRECTION };
+
 enum GmStage { GM_START = 1, GM_BASIS, GM_ORTHO, GM_FINISH, GM_RESIDUAL, GM_ADD_Z };
 
 // single-reduction CG: slots per reduced quantity that the workgroups of a launch add into
@@ -184,6 +194,8 @@ struct fe_problem {
   int precond = FE_PC_JACOBI; // FE_PC_JACOBI or FE_PC_BLOCK_JACOBI
   void* w_blk = nullptr;      // inverse node blocks [n_nodes][6] (allocated on first use)
   void* w_ilu = nullptr;      // ILU(0) factors [27][9][n_nodes] (allocated by fe_set_preconditioner)
+  void* w_ipcg = nullptr;     // CG with ILU(0): r, p, q, z [n_dof] each
+  fe::IpcgCtrl* ipcg = nullptr;
   void* w_gm = nullptr;       // GMRES: basis [gm_cap + 1][n_dof], then w and z [n_dof] each
   int gm_cap = 0;             // restart length w_gm was sized for
   fe::GmresDev* gm_dev = nullptr; // GMRES scalars (device)
@@ -315,6 +327,11 @@ void* gm_work_z(const fe_problem* p);
 // z = M^-1 r with the point (diagonal in w_d, not inverted) or node-block (inverted
 // blocks in w_blk) preconditioner as set up last (fe_krylov.hip)
 hipError_t pc_apply(const fe_problem* p, const void* r, void* z, hipStream_t s);
+// CG with ILU(0) (fe_krylov.hip): one stage per call (IpcgStage); k = iteration index;
+// vector v of the workspace: 0 r, 1 p, 2 q, 3 z
+hipError_t ipcg_step(const fe_problem* p, int stage, long k, const void* b, void* x, double rtol, int max_it,
+                     hipStream_t s);
+void* ipcg_vec(const fe_problem* p, int v);
 // node-block ILU(0) in 8-colour order (fe_ilu.hip): factor from the CSR matrix, apply
 // z = (L U)^-1 r (r may equal z; 16 launches, which return at once when *stop is set)
 size_t ilu_words(const fe_problem* p);

@@ -399,6 +399,167 @@ hipError_t pc_apply_t(const fe_problem* p, const void* r, void* z, hipStream_t s
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// CG with a preconditioner applied by separate launches (ILU(0)): Hestenes & Stiefel
+// recursion with z = M^-1 r, FP64 dots in fixed order, device-resident scalars.
+
+template <typename T>
+__global__ __launch_bounds__(KB) void ipcg_init_kernel(int64_t n, const T* b, T* x, T* r, T* q, double* part,
+                                                       IpcgCtrl* c, double rtol, int max_it) {
+  __shared__ double sh[KB / 64];
+  double v = 0;
+  for (int64_t d = (int64_t)blockIdx.x * KB + threadIdx.x; d < n; d += (int64_t)gridDim.x * KB) {
+    x[d] = 0;
+    q[d] = 0;
+    const T t = b[d];
+    r[d] = t;
+    v += (double)t * (double)t;
+  }
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+#pragma unroll
+    for (int q = 0; q < KB / 64; ++q) t += sh[q];
+    part[blockIdx.x] = t;
+    if (blockIdx.x == 0) {
+      c->rtol = rtol;
+      c->max_it = max_it;
+      c->iters = 0;
+      c->status = CG_RUNNING;
+      c->alpha = c->pq = 0;
+      c->rzs[0] = c->rzs[1] = 0;
+    }
+  }
+}
+
+// ||r||^2 from the partials; the first call sets ||b|| and the tolerance, later calls
+// count the finished iteration and test it.
+__global__ __launch_bounds__(KB) void ipcg_check_kernel(const double* part, int np, IpcgCtrl* c, int first) {
+  __shared__ double sh[KB / 64];
+  if (c->status) return;
+  const double rr = group_sum(part, np, sh);
+  if (threadIdx.x != 0) return;
+  c->rr = rr;
+  if (!is_finite(rr)) {
+    c->status = FE_ERR_NONFINITE;
+    return;
+  }
+  if (first) {
+    c->bb = rr;
+    c->tol2 = c->rtol * c->rtol * rr;
+    if (rr == 0.0) c->status = CG_CONVERGED;
+    else if (c->max_it <= 0) c->status = FE_ERR_NOT_CONVERGED;
+    return;
+  }
+  c->iters += 1;
+  if (rr <= c->tol2) c->status = CG_CONVERGED;
+  else if (c->iters >= c->max_it) c->status = FE_ERR_NOT_CONVERGED;
+}
+
+// p = z + beta p with beta = (r, z)_k / (r, z)_{k-1} (k = 0: p = z); every workgroup sums the
+// (r, z) partials itself, workgroup 0 records them in slot k & 1.  q is cleared for the
+// next operator application (the matrix-free operator adds into it).
+template <typename T>
+__global__ __launch_bounds__(KB) void ipcg_direction_kernel(int64_t n, const T* z, T* p, T* q, const double* part,
+                                                            int np, IpcgCtrl* c, long k) {
+  __shared__ double sh[KB / 64];
+  if (c->status) return;
+  const double rz = group_sum(part, np, sh);
+  const double beta = k == 0 ? 0.0 : rz / c->rzs[(k - 1) & 1];
+  if (!is_finite(rz) || !is_finite(beta)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) c->status = FE_ERR_NONFINITE;
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) c->rzs[k & 1] = rz;
+  const T bt = T(beta);
+  for (int64_t d = (int64_t)blockIdx.x * KB + threadIdx.x; d < n; d += (int64_t)gridDim.x * KB) {
+    p[d] = k == 0 ? z[d] : z[d] + bt * p[d];
+    q[d] = 0;
+  }
+}
+
+// alpha = (r, z)_k / (p, A p) (every workgroup sums the partials itself), x += alpha p,
+// r -= alpha q, partials of ||r||^2.
+template <typename T>
+__global__ __launch_bounds__(KB) void ipcg_update_kernel(int64_t n, const T* p, const T* q, T* x, T* r,
+                                                         const double* part_pq, int np, IpcgCtrl* c, long k,
+                                                         double* part_rr) {
+  __shared__ double sh[KB / 64];
+  if (c->status) return;
+  const double pq = group_sum(part_pq, np, sh);
+  if (!(pq > 0.0) || !is_finite(pq)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) c->status = is_finite(pq) ? FE_ERR_BREAKDOWN : FE_ERR_NONFINITE;
+    return;
+  }
+  const double alpha = c->rzs[k & 1] / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c->alpha = alpha;
+    c->pq = pq;
+  }
+  const T a = T(alpha);
+  double v = 0;
+  for (int64_t d = (int64_t)blockIdx.x * KB + threadIdx.x; d < n; d += (int64_t)gridDim.x * KB) {
+    x[d] += a * p[d];
+    const T t = r[d] - a * q[d];
+    r[d] = t;
+    v += (double)t * (double)t;
+  }
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+#pragma unroll
+    for (int w = 0; w < KB / 64; ++w) t += sh[w];
+    part_rr[blockIdx.x] = t;
+  }
+}
+
+template <typename T> T* ipcg_v(const fe_problem* p, int v) {
+  return static_cast<T*>(p->w_ipcg) + (int64_t)v * p->n_dof;
+}
+
+template <typename T>
+hipError_t ipcg_step_t(const fe_problem* p, int stage, long k, const void* b, void* x, double rtol, int max_it,
+                       hipStream_t s) {
+  const int64_t n = p->n_dof;
+  double* part_pq = p->gm_part;
+  double* part_rr = p->gm_part + GM_GRID;
+  double* part_rz = p->gm_part + 2 * GM_GRID;
+  const int* stop = &p->ipcg->status;
+  T* r = ipcg_v<T>(p, 0);
+  T* pp = ipcg_v<T>(p, 1);
+  T* q = ipcg_v<T>(p, 2);
+  T* z = ipcg_v<T>(p, 3);
+  switch (stage) {
+    case IPCG_INIT:
+      hipLaunchKernelGGL(ipcg_init_kernel<T>, dim3(GM_GRID), dim3(KB), 0, s, n, static_cast<const T*>(b),
+                         static_cast<T*>(x), r, q, part_rr, p->ipcg, rtol, max_it);
+      break;
+    case IPCG_CHECK_FIRST:
+    case IPCG_CHECK:
+      hipLaunchKernelGGL(ipcg_check_kernel, dim3(1), dim3(KB), 0, s, part_rr, GM_GRID, p->ipcg,
+                         stage == IPCG_CHECK_FIRST ? 1 : 0);
+      break;
+    case IPCG_FIRST_DIRECTION:  // (r, z) partials, then p = z
+    case IPCG_DIRECTION:
+      hipLaunchKernelGGL(gm_dots_kernel<T>, dim3(GM_GRID), dim3(KB), 0, s, n, r, 1, z, part_rz, stop);
+      hipLaunchKernelGGL(ipcg_direction_kernel<T>, dim3(GM_GRID), dim3(KB), 0, s, n, z, pp, q, part_rz, GM_GRID,
+                         p->ipcg, stage == IPCG_FIRST_DIRECTION ? 0L : k);
+      break;
+    case IPCG_UPDATE:  // (p, q) partials, then the step
+      hipLaunchKernelGGL(gm_dots_kernel<T>, dim3(GM_GRID), dim3(KB), 0, s, n, pp, 1, q, part_pq, stop);
+      hipLaunchKernelGGL(ipcg_update_kernel<T>, dim3(GM_GRID), dim3(KB), 0, s, n, pp, q, static_cast<T*>(x), r,
+                         part_pq, GM_GRID, p->ipcg, k, part_rr);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t gm_setup_t(const fe_problem* p, const void* b, void* x, double rtol, int max_it, int m, hipStream_t s) {
   hipLaunchKernelGGL(gm_setup_kernel<T>, dim3(GM_GRID), dim3(KB), 0, s, p->n_dof, static_cast<const T*>(b),
@@ -412,6 +573,16 @@ hipError_t gm_setup_t(const fe_problem* p, const void* b, void* x, double rtol, 
 hipError_t gm_setup(const fe_problem* p, const void* b, void* x, double rtol, int max_it, int m, hipStream_t s) {
   return p->prec == FE_F64 ? gm_setup_t<double>(p, b, x, rtol, max_it, m, s)
                            : gm_setup_t<float>(p, b, x, rtol, max_it, m, s);
+}
+
+hipError_t ipcg_step(const fe_problem* p, int stage, long k, const void* b, void* x, double rtol, int max_it,
+                     hipStream_t s) {
+  return p->prec == FE_F64 ? ipcg_step_t<double>(p, stage, k, b, x, rtol, max_it, s)
+                           : ipcg_step_t<float>(p, stage, k, b, x, rtol, max_it, s);
+}
+
+void* ipcg_vec(const fe_problem* p, int v) {
+  return static_cast<char*>(p->w_ipcg) + (size_t)v * p->n_dof * (p->prec == FE_F64 ? 8 : 4);
 }
 
 hipError_t pc_apply(const fe_problem* p, const void* r, void* z, hipStream_t s) {

@@ -1,8 +1,8 @@
 """Device preconditioners against the oracle: z = M^-1 r for point Jacobi, node-block
 Jacobi and the 8-colour node-block ILU(0) (FP64 and FP32) on the config-1 CSR matrix;
-GMRES with ILU(0) against the oracle's GMRES with the oracle's ILU(0); a Newton ramp
-with GMRES + ILU(0) inner solves; the 64^3 plastic fiber RVE; and the rejected
-combinations."""
+GMRES and CG with ILU(0) against the oracle's solvers with the oracle's ILU(0); Newton
+ramps with GMRES + ILU(0) and CG + ILU(0) inner solves; the 64^3 plastic fiber RVE; and
+the rejected combinations."""
 import numpy as np
 import pytest
 
@@ -78,15 +78,33 @@ def test_gmres_ilu_matches_oracle():
     assert rel_err(x.cpu().numpy(), x_ref) <= 1e-8
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cg_ilu_matches_oracle(prec):
+    """CG with ILU(0) (symmetric operator, so M = L D L^T is symmetric) against the oracle's
+    CG with the oracle's ILU(0): iteration count and solution."""
+    from paper_2604_22087_amd import fe
+    n, rve, k_e, rhs, P, b, csr = _config1(prec)
+    rp, ci, v = rve.bc_csr(k_e)
+    rtol = 1e-11 if prec == "f64" else 1e-5
+    x_ref, it_ref, st, _ = solver.pcg(lambda x: assembly.csr_matvec(rp, ci, v, x), None, rhs, rtol, 2000,
+                                      precond=ilu.bilu0_preconditioner(n, rp, ci, v))
+    assert st == solver.OK
+    P.set_preconditioner(fe.PC_ILU0)
+    x, res = P.pcg(b, op=fe.OP_CSR, csr=csr, rtol=rtol, max_it=2000)
+    print(f"  CG + ILU(0) {prec}: iterations {res.iterations} (oracle {it_ref})", flush=True)
+    assert res.status == 0 and abs(res.iterations - it_ref) <= (1 if prec == "f64" else 3)
+    assert rel_err(x.double().cpu().numpy(), x_ref) <= (1e-9 if prec == "f64" else 1e-4)
+
+
 def test_ilu_rejected_combinations():
     import torch
     from paper_2604_22087_amd import fe
     n, rve, k_e, rhs, P, b, csr = _config1()
     P.set_preconditioner(fe.PC_ILU0)
     with pytest.raises(fe.FeError):
-        P.pcg(b, op=fe.OP_CSR, csr=csr)                       # CG does not take ILU(0)
-    with pytest.raises(fe.FeError):
         P.pcg(b, op=fe.OP_CSR, csr=csr, solver=fe.SOLVER_BICGSTAB)
+    with pytest.raises(fe.FeError):
+        P.pcg(b, op=fe.OP_MATFREE)                            # no CSR values to factor
     with pytest.raises(fe.FeError):
         P.pcg(b, op=fe.OP_MATFREE, solver=fe.SOLVER_GMRES)    # no CSR values to factor
     with pytest.raises(fe.FeError):
@@ -104,7 +122,8 @@ def test_newton_gmres_ilu_matches_cg():
     phase = inputs.sphere_phase(n)
     models, params = lib_materials([("j2", 3.5, 0.35, 0.05, 0.1), ("linear", 70.0, 0.22)])
     out = {}
-    for name, pc, solv in (("cg", fe.PC_JACOBI, fe.SOLVER_CG), ("gmres-ilu", fe.PC_ILU0, fe.SOLVER_GMRES)):
+    for name, pc, solv in (("cg", fe.PC_JACOBI, fe.SOLVER_CG), ("gmres-ilu", fe.PC_ILU0, fe.SOLVER_GMRES),
+                           ("cg-ilu", fe.PC_ILU0, fe.SOLVER_CG)):
         P = fe.Problem(n, "f64")
         P.set_materials(torch.tensor(phase, device="cuda"), models, params)
         P.set_dirichlet(torch.tensor(inputs.boundary_dof_mask(n), device="cuda"))
@@ -115,8 +134,9 @@ def test_newton_gmres_ilu_matches_cg():
         out[name] = (np.array(sig), info)
         print(f"  {name}: {info}", flush=True)
         assert info["steps_done"] == len(path)
-    assert out["gmres-ilu"][1]["pcg_iterations"] < out["cg"][1]["pcg_iterations"]
-    assert np.max(np.abs(out["gmres-ilu"][0] - out["cg"][0])) <= 1e-9 * np.max(np.abs(out["cg"][0]))
+    for name in ("gmres-ilu", "cg-ilu"):
+        assert out[name][1]["pcg_iterations"] < out["cg"][1]["pcg_iterations"]
+        assert np.max(np.abs(out[name][0] - out["cg"][0])) <= 1e-9 * np.max(np.abs(out["cg"][0]))
 
 
 def test_gmres_ilu_fiber64():
@@ -151,3 +171,14 @@ def test_gmres_ilu_fiber64():
         assert r.status == 0 and true <= 2e-8
     assert res["ilu"][0] < res["jacobi"][0]
     assert float(torch.linalg.norm(res["ilu"][2] - res["jacobi"][2]) / torch.linalg.norm(res["jacobi"][2])) <= 1e-5
+    # CG: ILU(0) (unfused) against the fused matrix-free Jacobi-CG
+    for name, pc, op in (("jacobi (fused, matrix-free)", fe.PC_JACOBI, fe.OP_MATFREE), ("ilu", fe.PC_ILU0, fe.OP_CSR)):
+        P.set_preconditioner(pc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, r = P.pcg(b, op=op, csr=csr if op == fe.OP_CSR else None, rtol=1e-8, max_it=20000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        true = float(torch.linalg.norm(b - P.apply_csr(*csr, x)) / torch.linalg.norm(b))
+        print(f"  64^3 CG {name}: {r.iterations} iterations, {dt:.3f} s, true residual {true:.2e}", flush=True)
+        assert r.status == 0 and true <= 2e-8
