@@ -130,7 +130,6 @@ void fe_problem_destroy(fe_problem* p) {
   free_dev(p->u_lin);
   free_dev(p->w_r);
   free_dev(p->w_p);
-  free_dev(p->w_p2);
   free_dev(p->w_q);
   free_dev(p->w_d);
   free_dev(p->w_blk);
@@ -190,7 +189,7 @@ int fe_problem_create(fe_problem** out, int n, int precision) {
       std::max<size_t>({(size_t)2 * 1024, (size_t)std::max<int64_t>(elem_grid_size(n), SPMV_MAXGRID) + 2 * CG_UGRID,
                         (size_t)9 * CGS_SLOTS});
   if ((st = alloc((void**)&p->phase, p->n_el)) || (st = alloc(&p->w_r, vec)) || (st = alloc(&p->w_p, vec)) ||
-      (st = alloc(&p->w_p2, vec)) || (st = alloc(&p->w_q, vec)) || (st = alloc(&p->w_d, vec)) ||
+      (st = alloc(&p->w_q, vec)) || (st = alloc(&p->w_d, vec)) ||
       (st = alloc((void**)&p->partials, n_part * sizeof(double))) ||
       (st = alloc((void**)&p->counter, sizeof(unsigned int))) || (st = alloc((void**)&p->ctrl, sizeof(CgCtrl))) ||
       (st = alloc((void**)&p->stress_sum, 8 * sizeof(double))) || (st = alloc((void**)&p->flags, sizeof(int)))) {

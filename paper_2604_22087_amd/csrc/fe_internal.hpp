@@ -188,7 +188,6 @@ struct fe_problem {
   // solver workspace
   void* w_r = nullptr;
   void* w_p = nullptr;
-  void* w_p2 = nullptr;       // second search-direction buffer (fused matrix-free CG)
   void* w_q = nullptr;
   void* w_d = nullptr;        // inverse diagonal
   int precond = FE_PC_JACOBI; // FE_PC_JACOBI or FE_PC_BLOCK_JACOBI

@@ -1855,14 +1855,15 @@ hipError_t launch_dot(const fe_problem* p, const void* a, const void* b, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// Jacobi-preconditioned CG with device-resident scalars and no grid-wide fences.
+// Jacobi-preconditioned CG on the CSR operator, with device-resident scalars and no
+// grid-wide fences (the matrix-free solve runs the single-reduction form further down).
 // Every kernel of an iteration writes per-block partial sums; the next kernel
 // re-reduces them in every block in the same order (identical results in all
 // blocks; the kernel boundary makes the partials visible), and block 0 records
 // the scalars for the host.  Kernels return at once when ctrl->status is set, so
 // the host can enqueue several iterations between convergence checks.
 //   direction step k: rr, rz from the update partials -> stop tests, beta = rz / rz_old,
-//                     p = M^-1 r + beta p          (fused into the matrix-free operator)
+//                     p = M^-1 r + beta p
 //   operator k:       q = A p, partials of p.q
 //   update k:         alpha = rz / p.q, x += alpha p, r -= alpha q, q = 0, partials of r.r, r.M^-1 r
 
@@ -1906,7 +1907,7 @@ template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_init_kernel(
   }
 }
 
-// CSR path: direction step as a kernel of its own (the mat-vec needs the whole p first)
+// Direction step as a kernel of its own (the mat-vec needs the whole p first)
 template <typename T> __global__ __launch_bounds__(VBLOCK) void cg_direction_kernel(int64_t n, const T* r,
                                                                                      const T* dinv, int block, T* p,
                                                                                      CgCtrl* ctrl, const double* pu,
@@ -2029,12 +2030,6 @@ hipError_t cg_init(const fe_problem* p, const void* b, void* x, double rtol, int
 }
 
 int elem_grid_size(int n) { return elem_grid(n); }
-
-// Search-direction buffers of CG iteration k: the fused matrix-free iteration reads
-// p_old and writes p_new, alternating between w_p and w_p2; the CSR iteration keeps p in w_p.
-static void* cg_p_new(const fe_problem* p, int op, long k) {
-  return (op == FE_OP_CSR || (k & 1)) ? p->w_p : p->w_p2;
-}
 
 // CG mat-vec: q = A p with LPR lanes per row (grid-stride over rows) and per-workgroup partials of p.q.
 template <typename T, int LPR>
@@ -2201,7 +2196,7 @@ hipError_t cg_pre(const fe_problem* p, int op, long k, hipStream_t s) {
 
 template <typename T> static hipError_t cg_vectors_t(const fe_problem* p, int op, T* x, long k, hipStream_t s) {
   const int64_t n = p->n_dof;
-  T* P = (T*)cg_p_new(p, op, k);
+  T* P = (T*)p->w_p;
   hipLaunchKernelGGL(cg_update_kernel<T>, dim3(CG_UGRID), dim3(VBLOCK), 0, s, n, x, (T*)p->w_r, (const T*)P,
                      (T*)p->w_q, (const T*)pc_buffer(p), p->precond, p->ctrl, (const double*)p->partials,
                      cg_operator_grid(p, op), p->partials + cg_pa_size(p), k);

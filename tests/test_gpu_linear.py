@@ -155,6 +155,42 @@ def test_profile_sampling_inside_cg(op):
         P.profile(-1)
 
 
+@pytest.mark.parametrize("pc", ["jacobi", "block"])
+def test_fused_cg_iterates_match_textbook_pcg(pc):
+    """The matrix-free solve runs single-reduction CG (one fused launch per iteration); its
+    iterate after k iterations equals the oracle's textbook PCG iterate x_k (same
+    recursion in exact arithmetic), for k below convergence, and b = 0 returns at once."""
+    import torch
+    from paper_2604_22087_amd import fe
+    n = 8
+    print(f"[fused cg iterates] pc={pc}", flush=True)
+    phase = inputs.sphere_phase(n)
+    rve = RVE(n, phase, oracle_phases(PHASES_CONFIG1))
+    eb = np.diag([0.01, 0.0, 0.0])
+    r_e, k_e, _ = rve.element_residual_tangent(rve.affine_lift(eb))
+    rhs = -assembly.assemble_vector(rve.conn, r_e, rve.n_dof) * rve.free
+    apply_a = lambda x: solver.matfree_apply(rve.conn, k_e, x, rve.mask)
+    d = solver.matfree_diagonal(rve.conn, k_e, rve.n_dof, rve.mask)
+    pre = solver.block_jacobi(solver.matfree_node_blocks(rve.conn, k_e, rve.n_dof, rve.mask)) if pc == "block" \
+        else None
+    P = _problem(n, "f64", phase)
+    P.set_dirichlet(torch.tensor(inputs.boundary_dof_mask(n), device="cuda"))
+    if pc == "block":
+        P.set_preconditioner(fe.PC_BLOCK_JACOBI)
+    u = P.vector()
+    P.lift(eb, u, zero_free=True)
+    b = P.residual(u, apply_bc=True, store_tangent=True)
+    b.neg_()
+    for k in (1, 2, 7, 25):
+        x_ref, it_ref, st, _ = solver.pcg(apply_a, d, rhs, 1e-30, k, precond=pre)
+        assert it_ref == k and st == solver.NOT_CONVERGED
+        x, res = P.pcg(b, op=fe.OP_MATFREE, rtol=1e-30, max_it=k, check=False)
+        assert res.iterations == k and res.status == 4
+        assert rel_err(_np(x), x_ref) <= 1e-10, k
+    x, res = P.pcg(P.vector(), op=fe.OP_MATFREE, rtol=1e-10)
+    assert res.status == 0 and res.iterations == 0 and not x.any()
+
+
 def test_scale_field_and_vjp():
     """Per-element modulus scale; vjp_e = lambda_e . K_hat_e u_e against the oracle."""
     n = 6
