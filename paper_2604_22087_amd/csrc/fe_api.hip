@@ -138,6 +138,7 @@ void fe_problem_destroy(fe_problem* p) {
   free_dev(p->w_gm);
   free_dev(p->w_ilu);
   free_dev(p->w_ipcg);
+  free_dev(p->nodal_flag);
   free_dev(p->ipcg);
   free_dev(p->gm_dev);
   free_dev(p->gm_part);
@@ -533,11 +534,27 @@ int fe_set_preconditioner(fe_problem* p, int kind) {
 // word every `chunk` iterations (iterations after convergence are no-ops).
 // The Jacobi diagonal comes from the CSR matrix when one is given (rp != null),
 // else from the element kernel; `op` selects the operator inside the iteration.
+// Solvers on a CSR operator use the node-structured mat-vec when rows 3a..3a+2 of the
+// matrix share their column list (always so for fe_csr_indices' pattern); one check per solve.
+static int detect_csr_structure(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, hipStream_t s) {
+  p->csr_nodal = 0;
+  if (op != FE_OP_CSR || !rp) return FE_OK;
+  if (!p->nodal_flag && alloc((void**)&p->nodal_flag, sizeof(int))) return FE_ERR_OOM;
+  HIPCHK(hipMemsetAsync(p->nodal_flag, 0, sizeof(int), s));
+  HIPCHK(launch_csr_nodal_check(p, rp, ci, p->nodal_flag, s));
+  int* h = reinterpret_cast<int*>(p->host_buf);
+  HIPCHK(hipMemcpyAsync(h, p->nodal_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  p->csr_nodal = *h == 0 ? 1 : 0;
+  return FE_OK;
+}
+
 // CG with the ILU(0) preconditioner (applied by its own sweeps, so not fused into the
 // operator launch): per iteration q = A p, step, test, z = (L U)^-1 r, new direction.
 static int ipcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, const void* b,
                     void* x, double rtol, int max_it, fe_pcg_info* info, hipStream_t s, int* applies) {
   if (!rp) return arg_error("FE_PC_ILU0 needs the assembled CSR matrix");
+  if (int e = detect_csr_structure(p, op, rp, ci, s)) return e;
   if (!p->w_ipcg && alloc(&p->w_ipcg, 4 * real_size(p) * (size_t)p->n_dof)) return FE_ERR_OOM;
   if (!p->ipcg && alloc((void**)&p->ipcg, sizeof(IpcgCtrl))) return FE_ERR_OOM;
   if (!p->gm_part && alloc((void**)&p->gm_part, (size_t)(GM_MAXM + 1) * GM_GRID * sizeof(double)))
@@ -595,6 +612,7 @@ static int ipcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci,
 static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, const void* b,
                    void* x, double rtol, int max_it, fe_pcg_info* info, hipStream_t s, int* applies) {
   if (p->precond == FE_PC_ILU0) return ipcg_run(p, op, rp, ci, vals, b, x, rtol, max_it, info, s, applies);
+  if (int e = detect_csr_structure(p, op, rp, ci, s)) return e;
   if (p->precond == FE_PC_BLOCK_JACOBI) {
     HIPCHK(launch_block_jacobi(p, rp, ci, vals, p->w_blk, s));
   } else if (rp) {
@@ -672,6 +690,7 @@ static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, 
 static int bicg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, const void* b,
                     void* x, double rtol, int max_it, fe_pcg_info* info, hipStream_t s, int* applies) {
   if (p->precond == FE_PC_ILU0) return arg_error("FE_PC_ILU0 is applied by fe_gmres and fe_pcg only");
+  if (int e = detect_csr_structure(p, op, rp, ci, s)) return e;
   const size_t rs = real_size(p);
   if (!p->w_bicg && alloc(&p->w_bicg, 8 * rs * (size_t)p->n_dof)) return FE_ERR_OOM;
   if (!p->bicg_part && alloc((void**)&p->bicg_part, 6 * BICG_GRID * sizeof(double))) return FE_ERR_OOM;
@@ -737,12 +756,10 @@ static int bicg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci,
 // x += M^-1 V y runs and, unless stopped, the next cycle starts from b - A x.
 static int gmres_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, const void* b,
                      void* x, double rtol, int max_it, int m, fe_pcg_info* info, hipStream_t s, int* applies) {
+  if (int e = detect_csr_structure(p, op, rp, ci, s)) return e;
   const size_t rs = real_size(p);
   if (p->w_gm && p->gm_cap < m) {
     free_dev(p->w_gm);
-  free_dev(p->w_ilu);
-  free_dev(p->w_ipcg);
-  free_dev(p->ipcg);
     p->w_gm = nullptr;
   }
   if (!p->w_gm) {
@@ -1094,8 +1111,9 @@ extern "C" int fe_profile_read(fe_problem* p, double* out) {
 // Algorithmic bytes of one operator launch at the current linearisation.
 static int operator_bytes(fe_problem* p, int op, hipStream_t s, double* bytes) {
   const double w = (double)real_size(p);
-  if (op == FE_OP_CSR) {
-    *bytes = (w + 4.0) * (double)p->nnz + 4.0 * (double)(p->n_dof + 1) + 2.0 * w * (double)p->n_dof;
+  if (op == FE_OP_CSR) {  // one column list per node triple in the node-structured mat-vec
+    *bytes = (w + (p->csr_nodal ? 4.0 / 3.0 : 4.0)) * (double)p->nnz + 4.0 * (double)(p->n_dof + 1) +
+             2.0 * w * (double)p->n_dof;
     return FE_OK;
   }
   int64_t st[2] = {0, 0};

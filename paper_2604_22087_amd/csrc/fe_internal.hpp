@@ -192,6 +192,8 @@ struct fe_problem {
   void* w_d = nullptr;        // inverse diagonal
   int precond = FE_PC_JACOBI; // FE_PC_JACOBI or FE_PC_BLOCK_JACOBI
   void* w_blk = nullptr;      // inverse node blocks [n_nodes][6] (allocated on first use)
+  int csr_nodal = 0;          // solver in progress: the CSR matrix given has the node-triple structure
+  int* nodal_flag = nullptr;  // device flag of the structure check
   void* w_ilu = nullptr;      // ILU(0) factors [27][9][n_nodes] (allocated by fe_set_preconditioner)
   void* w_ipcg = nullptr;     // CG with ILU(0): r, p, q, z [n_dof] each
   fe::IpcgCtrl* ipcg = nullptr;
@@ -296,6 +298,11 @@ inline void* pc_buffer(const fe_problem* p) { return p->precond == FE_PC_BLOCK_J
 hipError_t launch_lin_stats(const fe_problem* p, unsigned long long* out, hipStream_t s);
 // element / CSR operator launches that return at once while *stop is set (BiCGStab)
 hipError_t launch_elem_stop(const fe_problem* p, int op, const ElemArgs& a, const int* stop, hipStream_t s);
+// *flag <- 1 unless rows 3a, 3a+1, 3a+2 of every node share one column list (the flag is
+// cleared by the caller); with it, solvers use the node-structured mat-vec
+hipError_t launch_csr_nodal_check(const fe_problem* p, const int32_t* rp, const int32_t* ci, int* flag,
+                                  hipStream_t s);
+// solver mat-vec: node-structured when p->csr_nodal, else one row per LPR lanes
 hipError_t launch_spmv_stop(const fe_problem* p, const int32_t* rp, const int32_t* ci, const void* v,
                             const void* x, void* y, const int* stop, hipStream_t s);
 // BiCGStab pieces (see the kernels): init, then per iteration

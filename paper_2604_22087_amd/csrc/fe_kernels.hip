@@ -1596,8 +1596,33 @@ hipError_t launch_spmv(const fe_problem* p, const int32_t* rp, const int32_t* ci
 
 hipError_t launch_spmv_stop(const fe_problem* p, const int32_t* rp, const int32_t* ci, const void* v,
                             const void* x, void* y, const int* stop, hipStream_t s) {
+  if (p->csr_nodal)
+    return p->prec == FE_F64
+               ? launch_spmv_nodal_t(p, rp, ci, (const double*)v, (const double*)x, (double*)y, stop, s)
+               : launch_spmv_nodal_t(p, rp, ci, (const float*)v, (const float*)x, (float*)y, stop, s);
   return p->prec == FE_F64 ? launch_spmv_t(p, rp, ci, (const double*)v, (const double*)x, (double*)y, stop, s)
                            : launch_spmv_t(p, rp, ci, (const float*)v, (const float*)x, (float*)y, stop, s);
+}
+
+// One wave per node: rows 3a, 3a+1, 3a+2 must have one length and one column list.
+__global__ __launch_bounds__(256) void csr_nodal_check_kernel(int64_t n_nodes, const int32_t* rp,
+                                                              const int32_t* ci, int* flag) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t nd = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; nd < n_nodes; nd += waves) {
+    const int b0 = rp[3 * nd], b1 = rp[3 * nd + 1], b2 = rp[3 * nd + 2], e = rp[3 * nd + 3];
+    bool bad = (b1 - b0 != b2 - b1) || (e - b2 != b1 - b0);
+    if (!bad)
+      for (int k = lane; k < b1 - b0; k += 64) bad = bad || ci[b0 + k] != ci[b1 + k] || ci[b0 + k] != ci[b2 + k];
+    if (bad) *flag = 1;
+  }
+}
+
+hipError_t launch_csr_nodal_check(const fe_problem* p, const int32_t* rp, const int32_t* ci, int* flag,
+                                  hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((p->n_nodes + 3) / 4, 4096);
+  hipLaunchKernelGGL(csr_nodal_check_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p->n_nodes, rp, ci, flag);
+  return hipGetLastError();
 }
 
 // Diagonal of a CSR matrix with sorted columns (binary search per row).
@@ -2060,8 +2085,50 @@ __global__ __launch_bounds__(256) void cg_spmv_kernel(int64_t n_rows, const int3
   if (threadIdx.x == 0) pa[blockIdx.x] = pq;
 }
 
+// Node-structured form of the same (rows 3a..3a+2 share their column list): LPN lanes per
+// node, grid-stride over node groups.
+template <typename T, int LPN>
+__global__ __launch_bounds__(256) void cg_spmv_nodal_kernel(int64_t n_nodes, const int32_t* __restrict__ rp,
+                                                            const int32_t* __restrict__ ci, const T* __restrict__ v,
+                                                            const T* __restrict__ p, T* __restrict__ q,
+                                                            const int* stop, double* pa) {
+  __shared__ double sh[VBLOCK / 64];
+  if (*stop) return;
+  constexpr int NPB = 256 / LPN;
+  const int lane = threadIdx.x % LPN;
+  double pq = 0;
+  for (int64_t n0 = (int64_t)blockIdx.x * NPB; n0 < n_nodes; n0 += (int64_t)gridDim.x * NPB) {
+    const int64_t nd = n0 + threadIdx.x / LPN;
+    T a0 = 0, a1 = 0, a2 = 0;
+    if (nd < n_nodes) {
+      const int b0 = rp[3 * nd], b1 = rp[3 * nd + 1], b2 = rp[3 * nd + 2];
+      const int len = b1 - b0;
+      for (int k = lane; k < len; k += LPN) {
+        const T xv = p[ci[b0 + k]];
+        a0 += v[b0 + k] * xv;
+        a1 += v[b1 + k] * xv;
+        a2 += v[b2 + k] * xv;
+      }
+    }
+#pragma unroll
+    for (int off = LPN / 2; off > 0; off >>= 1) {
+      a0 += __shfl_xor(a0, off, LPN);
+      a1 += __shfl_xor(a1, off, LPN);
+      a2 += __shfl_xor(a2, off, LPN);
+    }
+    if (nd < n_nodes && lane < 3) {
+      const T a = lane == 0 ? a0 : (lane == 1 ? a1 : a2);
+      q[3 * nd + lane] = a;
+      pq += (double)p[3 * nd + lane] * (double)a;
+    }
+  }
+  pq = block_sum(pq, sh);
+  if (threadIdx.x == 0) pa[blockIdx.x] = pq;
+}
+
 static int cg_spmv_grid(const fe_problem* p) {
-  const int64_t blocks = (p->n_dof + (256 / SPMV_LPR) - 1) / (256 / SPMV_LPR);
+  const int64_t blocks = p->csr_nodal ? (p->n_nodes + (256 / SPMV_LPN) - 1) / (256 / SPMV_LPN)
+                                      : (p->n_dof + (256 / SPMV_LPR) - 1) / (256 / SPMV_LPR);
   return (int)std::min<int64_t>(blocks, SPMV_MAXGRID);
 }
 
@@ -2076,8 +2143,12 @@ static hipError_t cg_operator_t(const fe_problem* p, int op, const int32_t* rp, 
   T* Q = (T*)p->w_q;
   double* pa = p->partials;
   if (op == FE_OP_CSR) {
-    timed_launch((cg_spmv_kernel<T, SPMV_LPR>), dim3(cg_spmv_grid(p)), dim3(256), 0, s, p->n_dof, rp, ci, vals,
-                       (const T*)p->w_p, Q, stop, pa);
+    if (p->csr_nodal)
+      timed_launch((cg_spmv_nodal_kernel<T, SPMV_LPN>), dim3(cg_spmv_grid(p)), dim3(256), 0, s, p->n_nodes, rp, ci,
+                   vals, (const T*)p->w_p, Q, stop, pa);
+    else
+      timed_launch((cg_spmv_kernel<T, SPMV_LPR>), dim3(cg_spmv_grid(p)), dim3(256), 0, s, p->n_dof, rp, ci, vals,
+                   (const T*)p->w_p, Q, stop, pa);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;  // the matrix-free operator runs through cgs_operator

@@ -76,6 +76,13 @@ def test_gmres_ilu_matches_oracle():
     assert res.status == 0 and abs(res.iterations - it_ref) <= 2
     assert res.iterations < res_j.iterations
     assert rel_err(x.cpu().numpy(), x_ref) <= 1e-8
+    # a longer restart reallocates the GMRES basis only; the ILU factors and the CG
+    # workspaces stay valid for the solves that follow
+    P.set_preconditioner(fe.PC_ILU0)
+    for kw in (dict(solver=fe.SOLVER_GMRES, restart=50), dict(solver=fe.SOLVER_CG), dict(solver=fe.SOLVER_GMRES,
+                                                                                           restart=64)):
+        x2, r2 = P.pcg(b, op=fe.OP_CSR, csr=csr, rtol=1e-11, max_it=2000, **kw)
+        assert r2.status == 0 and rel_err(x2.cpu().numpy(), x_ref) <= 1e-8
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
