@@ -10,10 +10,9 @@
 //      nodal differences give all 72 gradient entries);
 //   3. the constitutive law turns each gradient into a stress, which is pushed
 //      back to the nodes by the transposed factorisation;
-//   4. nodal forces are summed into LDS: FP64 by workgroup-scope LDS atomic adds,
-//      FP32 in 8 colour passes (elements of equal index parity share no node, so
-//      a pass has no conflicts); nodes owned by the brick alone are stored, nodes
-//      on the brick's faces are added with hardware FP atomics.
+//   4. nodal forces are summed into LDS in FP64 by workgroup-scope LDS atomic adds;
+//      nodes owned by the brick alone are stored, nodes on the brick's faces are
+//      added with hardware FP atomics.
 // Bricks are numbered so that consecutive bricks land on one XCD (workgroups
 // are dealt round-robin over the 8 XCDs), keeping shared face nodes in one L2.
 #include "fe_internal.hpp"
@@ -536,7 +535,7 @@ constexpr int STAGE_IT = (NN * 3 + EBLOCK - 1) / EBLOCK;
 
 template <typename T, bool NEED_L>
 __device__ __forceinline__ void cg_stage_brick(const ElemArgs& a, int n, int a0, int b0, int c0, T alpha, T beta,
-                                               T* s_x, T* s_y, T* s_b, T* s_l, double& g, double& rr) {
+                                               T* s_x, double* s_y, T* s_b, T* s_l, double& g, double& rr) {
   const T* __restrict__ RO = static_cast<const T*>(a.cg_rold);
   const T* __restrict__ WO = static_cast<const T*>(a.cg_wold);
   const T* __restrict__ SO = static_cast<const T*>(a.cg_sold);
@@ -712,7 +711,7 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
   constexpr bool APPLY_LIKE = (OP == OP_APPLY) || (OP == OP_CG_APPLY);
   constexpr bool NEED_L = (OP == OP_VJP) || (APPLY_LIKE && MS == MS_NH);
   __shared__ T s_x[NN * 3];
-  __shared__ T s_y[OP == OP_VJP ? 1 : NN * 3];
+  __shared__ double s_y[OP == OP_VJP ? 1 : NN * 3];  // nodal sums, FP64 in both precisions
   __shared__ T s_l[NEED_L ? NN * 3 : 1];
   __shared__ T s_b[OP == OP_CG_APPLY ? NN * 3 : 1];  // CG: u on constrained dofs (A u = u there)
   __shared__ double s_red[6][EBLOCK / 64];
@@ -1046,42 +1045,23 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
             pq += (double)Fo[k][j][i][c] * (double)s_x[3 * ((ex + i) + NX * ((ey + j) + NY * (ez + k))) + c];
   }
 
-  if constexpr (sizeof(T) == 8) {
-    // FP64 nodal sums in LDS: workgroup-scope atomic adds by all lanes at once (one corner
-    // per instruction, so the lanes of a wave address distinct nodes); measured 12 % faster
-    // per CG iteration than the colour passes below
-    if (valid) {
+  // nodal sums in LDS: workgroup-scope FP64 atomic adds by all lanes at once (one corner per
+  // instruction, so the lanes of a wave address distinct nodes); measured 12 % faster per
+  // FP64 CG iteration than 8 colour passes with a barrier each (FP32 float LDS atomics were
+  // twice as slow as the passes, hence FP64 sums for FP32 problems as well)
+  if (valid) {
 #pragma unroll
-      for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-              __hip_atomic_fetch_add(&s_y[3 * ((ex + i) + NX * ((ey + j) + NY * (ez + k))) + c], Fo[k][j][i][c],
-                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
-    __syncthreads();
-  } else {
-    // FP32: colour passes (equal index parity => no shared node); LDS float atomics
-    // measured twice as slow here
-    const int color = (ex & 1) | ((ey & 1) << 1) | ((ez & 1) << 2);
-    for (int col = 0; col < 8; ++col) {
-      if (valid && color == col) {
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-              for (int c = 0; c < 3; ++c)
-                s_y[3 * ((ex + i) + NX * ((ey + j) + NY * (ez + k))) + c] += Fo[k][j][i][c];
-      }
-      __syncthreads();
-    }
+          for (int c = 0; c < 3; ++c)
+            __hip_atomic_fetch_add(&s_y[3 * ((ex + i) + NX * ((ey + j) + NY * (ez + k))) + c],
+                                   (double)Fo[k][j][i][c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
+  __syncthreads();
 
   if (OP == OP_RESID && a.stress_sum && tid < 6) {
     double v = 0;
@@ -1113,9 +1093,9 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
       continue;
     }
     if (priv)
-      Y[dof] = s_y[i];
+      Y[dof] = T(s_y[i]);
     else
-      atomic_add(Y + dof, s_y[i]);
+      atomic_add(Y + dof, T(s_y[i]));
   }
   if (OP == OP_CG_APPLY) {  // partials of (u_j, A u_j), (r_j, u_j), ||r_j||^2
     const double t0 = block_sum(pq, &s_red[0][0]);
