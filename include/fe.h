@@ -180,12 +180,11 @@ int fe_diagonal(fe_problem* p, void* d, int apply_bc, void* stream);
  * triangular sweeps (Fig. 7 compares ILU with Jacobi on the assembled matrix);
  * it needs the CSR values (FE_OP_CSR, or fe_newton with assemble_csr), is
  * factored once per solve into 243 reals per node (allocated here; FE_ERR_OOM if
- * that fails) and is applied by fe_gmres and fe_pcg (CG then runs unfused: the
- * operator, the step, the two sweeps and the new direction as separate
- * launches; for symmetric A the factors satisfy U = D L^T, so M is symmetric);
- * fe_bicgstab returns FE_ERR_ARG with it; a singular pivot block sets bit 2 of
- * fe_read_flags and ends the solve with FE_ERR_NONFINITE.  FE_ERR_ARG for any
- * other kind. */
+ * that fails) and is applied by fe_gmres, fe_bicgstab and fe_pcg (CG then runs
+ * unfused: the operator, the step, the two sweeps and the new direction as
+ * separate launches; for symmetric A the factors satisfy U = D L^T, so M is
+ * symmetric); a singular pivot block sets bit 2 of fe_read_flags and ends the
+ * solve with FE_ERR_NONFINITE.  FE_ERR_ARG for any other kind. */
 int fe_set_preconditioner(fe_problem* p, int kind);
 
 /* z = M^-1 r for the preconditioner chosen by fe_set_preconditioner, set up as the

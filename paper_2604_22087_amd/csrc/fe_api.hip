@@ -689,13 +689,16 @@ static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, 
 // Preconditioned BiCGStab driver (same preconditioner set-up and polling as pcg_run).
 static int bicg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, const void* vals, const void* b,
                     void* x, double rtol, int max_it, fe_pcg_info* info, hipStream_t s, int* applies) {
-  if (p->precond == FE_PC_ILU0) return arg_error("FE_PC_ILU0 is applied by fe_gmres and fe_pcg only");
   if (int e = detect_csr_structure(p, op, rp, ci, s)) return e;
+  const bool ilu = p->precond == FE_PC_ILU0;
+  if (ilu && !rp) return arg_error("FE_PC_ILU0 needs the assembled CSR matrix");
   const size_t rs = real_size(p);
   if (!p->w_bicg && alloc(&p->w_bicg, 8 * rs * (size_t)p->n_dof)) return FE_ERR_OOM;
   if (!p->bicg_part && alloc((void**)&p->bicg_part, 6 * BICG_GRID * sizeof(double))) return FE_ERR_OOM;
   if (!p->bicg_ctrl && alloc((void**)&p->bicg_ctrl, sizeof(BicgCtrl))) return FE_ERR_OOM;
-  if (p->precond == FE_PC_BLOCK_JACOBI) {
+  if (ilu) {
+    HIPCHK(ilu_setup(p, rp, ci, vals, s));
+  } else if (p->precond == FE_PC_BLOCK_JACOBI) {
     HIPCHK(launch_block_jacobi(p, rp, ci, vals, p->w_blk, s));
   } else if (rp) {
     HIPCHK(launch_csr_diag(p, rp, ci, vals, p->w_d, s));
@@ -724,9 +727,11 @@ static int bicg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci,
   for (;;) {
     for (int c = 0; c < chunk; ++c) {
       HIPCHK(bicg_step(p, 0, x, s));  // direction
+      if (ilu) HIPCHK(ilu_apply(p, ph, ph, stop, s));
       HIPCHK(apply(ph, v));
       HIPCHK(bicg_step(p, 4, x, s));  // (r_hat, v)
       HIPCHK(bicg_step(p, 1, x, s));  // half step
+      if (ilu) HIPCHK(ilu_apply(p, sh, sh, stop, s));
       HIPCHK(apply(sh, t));
       HIPCHK(bicg_step(p, 2, x, s));  // (t, s), (t, t)
       HIPCHK(bicg_step(p, 3, x, s));  // update

@@ -2303,10 +2303,14 @@ template <typename T> struct BicgVec {
   int block;
 };
 
-// dst[node] = M^-1 v for one node (point Jacobi: inverse diagonal; node blocks: symmetric 3x3 inverse)
+// dst[node] = M^-1 v for one node (point Jacobi: inverse diagonal; node blocks: symmetric 3x3
+// inverse; ILU(0), block = 2: a copy, which the host then sweeps in place)
 template <typename T>
 __device__ __forceinline__ void bicg_precond(const BicgVec<T>& w, int64_t nd, const T v[3], T* dst) {
-  if (w.block) {
+  if (w.block == 2) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dst[3 * nd + c] = v[c];
+  } else if (w.block) {
     const T* m = w.M + 6 * nd;
     dst[3 * nd] = m[0] * v[0] + m[5] * v[1] + m[4] * v[2];
     dst[3 * nd + 1] = m[5] * v[0] + m[1] * v[1] + m[3] * v[2];
@@ -2498,14 +2502,14 @@ template <typename T> static BicgVec<T> bicg_vec(const fe_problem* p, void* x) {
   w.ph = base + 6 * n;
   w.sh = base + 7 * n;
   w.M = static_cast<const T*>(pc_buffer(p));
-  w.block = p->precond == FE_PC_BLOCK_JACOBI;
+  w.block = p->precond == FE_PC_BLOCK_JACOBI ? 1 : (p->precond == FE_PC_ILU0 ? 2 : 0);
   return w;
 }
 
 template <typename T>
 static hipError_t bicg_init_t(const fe_problem* p, const T* b, void* x, double rtol, int max_it, hipStream_t s) {
   hipLaunchKernelGGL(bicg_init_kernel<T>, dim3(BICG_GRID), dim3(VBLOCK), 0, s, p->n_dof, b, bicg_vec<T>(p, x),
-                     p->bicg_ctrl, p->bicg_part, rtol, max_it, p->precond == FE_PC_BLOCK_JACOBI ? 0 : 1);
+                     p->bicg_ctrl, p->bicg_part, rtol, max_it, p->precond == FE_PC_JACOBI ? 1 : 0);
   return hipGetLastError();
 }
 
