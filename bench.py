@@ -323,12 +323,13 @@ def cpu_baseline(n, phase, gpu_info, path):
     except Exception:  # pragma: no cover
         cores = 1
     rve = RVE(n, phase, [phase_params("j2", *MATRIX), phase_params("linear", *FIBER)])
-    u = rve.affine_lift(path[0])
+    samples = [0, len(path) // 2]  # the affine states of the first and a middle load step
     t0 = time.perf_counter()
-    r_e, k_e, _ = rve.element_residual_tangent(u, rve.zero_state())
-    t_rt = time.perf_counter() - t0
+    for k in samples:
+        r_e, k_e, _ = rve.element_residual_tangent(rve.affine_lift(path[k]), rve.zero_state())
+    t_rt = (time.perf_counter() - t0) / len(samples)
     x = np.random.default_rng(0).normal(size=rve.n_dof)
-    reps = 3
+    reps = 10
     t0 = time.perf_counter()
     for _ in range(reps):
         solver.matfree_apply(rve.conn, k_e, x, rve.mask)
@@ -336,9 +337,10 @@ def cpu_baseline(n, phase, gpu_info, path):
     applies, newton = gpu_info["operator_applies"], gpu_info["newton_iterations"] + len(path)
     t_step = t_rt * newton + t_apply * applies
     return {"value": rve.n_dof * applies / t_step / 1e9, "unit": "GDOF/s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"one residual+tangent evaluation ({t_rt:.1f} s) and {reps} matrix-free K*u "
-                       f"({t_apply:.2f} s each) of the {n}^3 workload at load step 1, scaled to the step's "
-                       f"{newton} residual/tangent evaluations and {applies} K*u"),
+            "sample": (f"{len(samples)} residual+tangent evaluations ({t_rt:.1f} s each) and {reps} matrix-free K*u "
+                       f"({t_apply:.2f} s each) of the {n}^3 workload at the affine states of load steps "
+                       f"{', '.join(str(k + 1) for k in samples)}, scaled to the step's {newton} residual/tangent "
+                       f"evaluations and {applies} K*u"),
             "qp_evals_per_s": 8 * rve.conn.shape[0] / t_rt, "step_seconds_est": t_step}
 
 
