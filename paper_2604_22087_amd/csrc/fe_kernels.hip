@@ -1419,14 +1419,26 @@ hipError_t launch_csr_pattern(const fe_problem* p, int32_t* row_ptr, int32_t* co
 
 // CSR values: one lane per (row node P, neighbour Q) 3x3 block, summed over the
 // elements that contain both nodes and their Gauss points (no atomics, deterministic).
+// Lane mapping: a workgroup takes TAN_NODES consecutive nodes and all 27 neighbour slots of
+// each, slot-major, with the slots ordered by how many elements the node pair shares (8 for
+// the node itself, then 4, 2, 1): the four waves hold the node itself and its 6 face
+// neighbours, 7 edge neighbours, 5 edge and 2 corner neighbours, 6 corner neighbours, so a
+// wave's lanes run (nearly) the same number of element iterations and read the stored
+// tangents of consecutive elements; the workgroup writes whole CSR row segments.
+constexpr int TAN_NODES = 9;
+constexpr int TAN_BLOCK = 256;  // 27 * TAN_NODES = 243 lanes used
+__constant__ int tan_slot_order[27] = {13, 4, 10, 12, 14, 16, 22,                        // self, faces
+                                       1, 3, 5, 7, 9, 11, 15, 17, 19, 21, 23, 25,       // edges
+                                       0, 2, 6, 8, 18, 20, 24, 26};                     // corners
+
 template <typename T, int MS>
-__global__ __launch_bounds__(256) void tangent_csr_kernel(TanArgs a, T* vals, int apply_bc) {
+__global__ __launch_bounds__(TAN_BLOCK) void tangent_csr_kernel(TanArgs a, T* vals, int apply_bc) {
   const int n = a.n;
   const int64_t np1 = n + 1;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= np1 * np1 * np1 * 27) return;
-  const int64_t P = t / 27;
-  const int s = (int)(t % 27);
+  if (threadIdx.x >= 27 * TAN_NODES) return;
+  const int64_t P = (int64_t)blockIdx.x * TAN_NODES + threadIdx.x % TAN_NODES;
+  if (P >= np1 * np1 * np1) return;
+  const int s = tan_slot_order[threadIdx.x / TAN_NODES];
   const int di = s % 3 - 1, dj = (s / 3) % 3 - 1, dk = s / 9 - 1;
   const int i = (int)(P % np1), j = (int)((P / np1) % np1), k = (int)(P / (np1 * np1));
   const int qi = i + di, qj = j + dj, qk = k + dk;
@@ -1468,20 +1480,20 @@ __global__ __launch_bounds__(256) void tangent_csr_kernel(TanArgs a, T* vals, in
 
 hipError_t launch_tangent_csr(const fe_problem* p, void* vals, int apply_bc, hipStream_t s) {
   const TanArgs a = tan_args(p);
-  const dim3 grid((unsigned)((p->n_nodes * 27 + 255) / 256));
+  const dim3 grid((unsigned)((p->n_nodes + TAN_NODES - 1) / TAN_NODES)), block(TAN_BLOCK);
   if (p->prec == FE_F64) {
     double* v = (double*)vals;
     switch (p->model_set) {
-      case MS_J2: timed_launch((tangent_csr_kernel<double, MS_J2>), grid, dim3(256), 0, s, a, v, apply_bc); break;
-      case MS_NH: timed_launch((tangent_csr_kernel<double, MS_NH>), grid, dim3(256), 0, s, a, v, apply_bc); break;
-      default: timed_launch((tangent_csr_kernel<double, MS_LINEAR>), grid, dim3(256), 0, s, a, v, apply_bc);
+      case MS_J2: timed_launch((tangent_csr_kernel<double, MS_J2>), grid, block, 0, s, a, v, apply_bc); break;
+      case MS_NH: timed_launch((tangent_csr_kernel<double, MS_NH>), grid, block, 0, s, a, v, apply_bc); break;
+      default: timed_launch((tangent_csr_kernel<double, MS_LINEAR>), grid, block, 0, s, a, v, apply_bc);
     }
   } else {
     float* v = (float*)vals;
     switch (p->model_set) {
-      case MS_J2: timed_launch((tangent_csr_kernel<float, MS_J2>), grid, dim3(256), 0, s, a, v, apply_bc); break;
-      case MS_NH: timed_launch((tangent_csr_kernel<float, MS_NH>), grid, dim3(256), 0, s, a, v, apply_bc); break;
-      default: timed_launch((tangent_csr_kernel<float, MS_LINEAR>), grid, dim3(256), 0, s, a, v, apply_bc);
+      case MS_J2: timed_launch((tangent_csr_kernel<float, MS_J2>), grid, block, 0, s, a, v, apply_bc); break;
+      case MS_NH: timed_launch((tangent_csr_kernel<float, MS_NH>), grid, block, 0, s, a, v, apply_bc); break;
+      default: timed_launch((tangent_csr_kernel<float, MS_LINEAR>), grid, block, 0, s, a, v, apply_bc);
     }
   }
   return hipGetLastError();
