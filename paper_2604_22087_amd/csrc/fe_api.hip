@@ -1168,7 +1168,7 @@ extern "C" int fe_set_surrogate(fe_problem* p, const float* W, double tol) {
     p->sur_cap = 0;
     const int64_t c = std::max<int64_t>(cap, 1);
     if (alloc((void**)&p->sur_x, sizeof(float) * 13 * c) || alloc((void**)&p->sur_y, sizeof(float) * 6 * c) ||
-        alloc((void**)&p->sur_jac, sizeof(float) * 36 * c) || alloc(&p->sur_D, real_size(p) * 36 * c))
+        alloc((void**)&p->sur_jac, sizeof(float) * 36 * c) || alloc(&p->sur_D, sizeof(float) * 36 * c))
       return FE_ERR_OOM;
     p->sur_cap = c;
   }

@@ -142,7 +142,7 @@ struct ElemArgs {
   float* sur_x;           // [cap][13] normalised network inputs
   float* sur_y;           // [cap][6] capture: normalised stress; consume: network output
   const float* sur_jac;   // [cap][6][6] network Jacobian (consume)
-  void* sur_D;            // [cap][36] real: symmetrised Voigt tangent of accepted points
+  void* sur_D;            // [cap][36] float: Voigt tangent of accepted points (symmetrised unless sur_full)
   unsigned int* sur_stats;// [2] accepted, fallback
   float sur_sin, sur_sout;
   double sur_tol;

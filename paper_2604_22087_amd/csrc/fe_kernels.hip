@@ -382,7 +382,7 @@ __device__ __forceinline__ void sur_inputs(const T H[3][3], const T epn[6], T an
 template <typename T>
 __device__ __forceinline__ bool sur_consume(const T H[3][3], const T epn[6], T an, T K, T G, T sy, T Hh,
                                             const float* y, const float* J, float s_in, float s_out, double tol,
-                                            const T tn[6], T S[3][3], T ep[6], T& al, T* Dsym, int full) {
+                                            const T tn[6], T S[3][3], T ep[6], T& al, float* Dsym, int full) {
   const T c[6] = {T(1), T(1), T(1), T(RSQ2), T(RSQ2), T(RSQ2)};
   T sig[6];
 #pragma unroll
@@ -424,22 +424,22 @@ __device__ __forceinline__ bool sur_consume(const T H[3][3], const T epn[6], T a
   for (int i = 0; i < 6; ++i)
 #pragma unroll
     for (int j = 0; j < 6; ++j)
-      Dsym[i * 6 + j] = full ? f * c[i] * c[j] * T(J[i * 6 + j])
-                             : T(0.5) * f * c[i] * c[j] * (T(J[i * 6 + j]) + T(J[j * 6 + i]));
+      Dsym[i * 6 + j] = float(full ? f * c[i] * c[j] * T(J[i * 6 + j])
+                             : T(0.5) * f * c[i] * c[j] * (T(J[i * 6 + j]) + T(J[j * 6 + i])));
   return true;
 }
 
 // Stress from a general Voigt tangent D (tensor stress, engineering shear strain) and sym(H).
 // (rare path inside the operator: rows are read one at a time so that this branch does
 // not raise the register budget of the whole kernel)
-template <typename T> __device__ __forceinline__ void general_apply(const T H[3][3], const T* D, T S[3][3]) {
+template <typename T> __device__ __forceinline__ void general_apply(const T H[3][3], const float* D, T S[3][3]) {
   const T e[6] = {H[0][0], H[1][1], H[2][2], H[1][2] + H[2][1], H[0][2] + H[2][0], H[0][1] + H[1][0]};
   T s[6];
 #pragma unroll 1
   for (int i = 0; i < 6; ++i) {
     T acc = 0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) acc += D[i * 6 + j] * e[j];
+    for (int j = 0; j < 6; ++j) acc += T(D[i * 6 + j]) * e[j];
     s[i] = acc;
   }
   S[0][0] = s[0];
@@ -894,7 +894,7 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
                   bool accepted = false, fallback = false;
                   if (ptrial && slot >= 0) {
                     T Ss[3][3], eps2[6], al2;
-                    T* Dsym = static_cast<T*>(a.sur_D) + (int64_t)slot * 36;
+                    float* Dsym = static_cast<float*>(a.sur_D) + (int64_t)slot * 36;
                     accepted = sur_consume(H, epn, an, Kb, Gs, sy, Hh, a.sur_y + (int64_t)slot * 6,
                                            a.sur_jac + (int64_t)slot * 36, a.sur_sin, a.sur_sout, a.sur_tol, tn,
                                            Ss, eps2, al2, Dsym, a.sur_full);
@@ -929,7 +929,7 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
               tn[0] = tq0[qp];
               if (tn[0] < T(-1.5)) {  // surrogate tangent of this point
                 const int slot = a.sur_map[(int64_t)qp * ne + e];
-                general_apply(H, static_cast<const T*>(a.sur_D) + (int64_t)slot * 36, S);
+                general_apply(H, static_cast<const float*>(a.sur_D) + (int64_t)slot * 36, S);
               } else {
 #pragma unroll
                 for (int k = 1; k < 6; ++k) tn[k] = pw[qp & 1][k - 1];
@@ -1176,7 +1176,7 @@ template <typename T> struct QpTangent {
   int kind;  // 0: small strain D = lp 1x1 + 2 mp I_sym - beta N x N; 1: Neo-Hookean at F; 2: general Voigt D
   T lp, mp, beta, N[6];
   T mu, lam, lnJ, FiT[3][3];
-  const T* D;
+  const float* D;  // kind 2: the surrogate's Voigt tangent (stored in FP32, as the network computes it)
 };
 
 template <typename T, int MS>
@@ -1197,7 +1197,7 @@ __device__ __forceinline__ void load_qp_tangent(const TanArgs& a, int64_t e, int
     for (int k = 0; k < 6; ++k) tn[k] = tg[(int64_t)(k * 8 + qp) * ne + e];
     if (tn[0] < T(-1.5)) {
       t.kind = 2;
-      t.D = static_cast<const T*>(a.sur_D) + (int64_t)a.sur_map[(int64_t)qp * ne + e] * 36;
+      t.D = static_cast<const float*>(a.sur_D) + (int64_t)a.sur_map[(int64_t)qp * ne + e] * 36;
     } else {
       j2_tangent_coeffs(tn, T(pc.K) * sc, T(pc.G) * sc, T(pc.H), t.lp, t.mp, t.beta, t.N);
     }
@@ -1231,7 +1231,7 @@ __device__ __forceinline__ void block_add(const QpTangent<T>& t, const T ga[3], 
       for (int k = 0; k < 3; ++k) {
         T s = 0;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) s += t.D[p * 6 + q] * Bb[q][k];
+        for (int q = 0; q < 6; ++q) s += T(t.D[p * 6 + q]) * Bb[q][k];
         DB[p][k] = s;
       }
 #pragma unroll
