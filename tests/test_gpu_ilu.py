@@ -133,6 +133,26 @@ def test_bicgstab_ilu_nonsymmetric_matches_oracle():
     assert rel_err(x.cpu().numpy(), x_ref) <= 1e-8
 
 
+def test_ilu_singular_pivot_is_reported():
+    """A zero diagonal block at an interior node makes its ILU(0) pivot singular: bit 2 of the
+    flags is raised and GMRES ends with FE_ERR_NONFINITE instead of returning garbage."""
+    import torch
+    from paper_2604_22087_amd import fe
+    n, rve, k_e, rhs, P, b, csr = _config1()
+    rp, ci, v = (t.cpu().numpy() for t in csr)
+    node = 4 + 9 * (4 + 9 * 4)  # the centre node of the 8^3 mesh (interior)
+    rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    blk = (rows // 3 == node) & (ci // 3 == node)
+    v = v.copy()
+    v[blk] = 0.0
+    csr0 = (csr[0], csr[1], torch.tensor(v, device="cuda"))
+    P.set_preconditioner(fe.PC_ILU0)
+    assert P.read_flags() == 0
+    _, res = P.pcg(b, op=fe.OP_CSR, csr=csr0, rtol=1e-10, max_it=100, check=False, solver=fe.SOLVER_GMRES)
+    assert res.status == 6  # FE_ERR_NONFINITE
+    assert P.read_flags() & 4
+
+
 def test_ilu_rejected_combinations():
     import torch
     from paper_2604_22087_amd import fe
