@@ -344,6 +344,16 @@ def cpu_baseline(n, phase, gpu_info, path):
             "qp_evals_per_s": 8 * rve.conn.shape[0] / t_rt, "step_seconds_est": t_step}
 
 
+def _leg(fn, *args):
+    """An optional leg: a failure there is recorded in its own entry and does not cost the
+    benchmark line."""
+    try:
+        return fn(*args)
+    except Exception as exc:  # noqa: BLE001 - reported in the JSON line
+        print(f"[bench] {fn.__name__} failed: {exc!r}", file=sys.stderr, flush=True)
+        return {"error": repr(exc)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -356,7 +366,7 @@ def main():
     ap.add_argument("--nh", type=int, default=0, help="also run the finite-strain Neo-Hookean leg at this n (0: skip)")
     ap.add_argument("--surrogate", type=int, default=96, help="n of the surrogate-vs-return-map leg (0: skip)")
     ap.add_argument("--adjoint-path", type=int, default=64, help="n of the plastic-path adjoint leg (0: skip)")
-    ap.add_argument("--inverse", type=int, default=0, help="n of the inverse-problem leg (0: skip)")
+    ap.add_argument("--inverse", type=int, default=64, help="n of the inverse-problem leg (0: skip)")
     ap.add_argument("--csr-sizes", default="96,128", help="mesh sizes of the assembled-operator leg ('' to skip)")
     ap.add_argument("--copy-calib", action="store_true", help="run only a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -452,20 +462,20 @@ def main():
         del P32
     if args.surrogate:
         print(f"[bench] surrogate leg {args.surrogate}^3", file=sys.stderr, flush=True)
-        out["surrogate"] = surrogate_leg(args.surrogate)
+        out["surrogate"] = _leg(surrogate_leg, args.surrogate)
     if args.csr_sizes:
         sizes = [int(v) for v in args.csr_sizes.split(",") if v]
         print(f"[bench] assembled-operator leg {sizes}", file=sys.stderr, flush=True)
-        out["csr_scaling"] = csr_scaling_leg(sizes)
+        out["csr_scaling"] = _leg(csr_scaling_leg, sizes)
     if args.adjoint_path:
         print(f"[bench] adjoint path leg {args.adjoint_path}^3", file=sys.stderr, flush=True)
-        out["adjoint_path"] = adjoint_path_leg(args.adjoint_path)
+        out["adjoint_path"] = _leg(adjoint_path_leg, args.adjoint_path)
     if args.inverse:
         print(f"[bench] inverse-problem leg {args.inverse}^3", file=sys.stderr, flush=True)
-        out["inverse"] = inverse_leg(args.inverse)
+        out["inverse"] = _leg(inverse_leg, args.inverse)
     if args.nh:
         print(f"[bench] neo-hookean leg {args.nh}^3", file=sys.stderr, flush=True)
-        out["neohooke"] = neohooke_leg(args.nh)
+        out["neohooke"] = _leg(neohooke_leg, args.nh)
     if not args.no_cpu:
         print("[bench] cpu oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(n, phase, infos[-1], path)
