@@ -189,6 +189,20 @@ def test_fused_cg_iterates_match_textbook_pcg(pc):
         assert rel_err(_np(x), x_ref) <= 1e-10, k
     x, res = P.pcg(P.vector(), op=fe.OP_MATFREE, rtol=1e-10)
     assert res.status == 0 and res.iterations == 0 and not x.any()
+    # FP32 vectors (FP64 dot products): the same iterates to FP32 accuracy
+    P32 = _problem(n, "f32", phase)
+    P32.set_dirichlet(torch.tensor(inputs.boundary_dof_mask(n), device="cuda"))
+    if pc == "block":
+        P32.set_preconditioner(fe.PC_BLOCK_JACOBI)
+    u32 = P32.vector()
+    P32.lift(eb, u32, zero_free=True)
+    b32 = P32.residual(u32, apply_bc=True, store_tangent=True)
+    b32.neg_()
+    for k in (1, 2, 7):
+        x_ref, _, _, _ = solver.pcg(apply_a, d, rhs, 1e-30, k, precond=pre)
+        x, res = P32.pcg(b32, op=fe.OP_MATFREE, rtol=1e-30, max_it=k, check=False)
+        assert res.iterations == k
+        assert rel_err(_np(x), x_ref) <= 1e-4, k
 
 
 def test_csr_solvers_with_and_without_node_structure():
