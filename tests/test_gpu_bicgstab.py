@@ -87,6 +87,30 @@ def test_bicgstab_nonsymmetric_csr():
     assert rel_err(x.cpu().numpy(), x_dense) <= 1e-9
 
 
+@pytest.mark.parametrize("solv", ["bicgstab", "gmres"])
+def test_nonsymmetric_solvers_fp32(solv):
+    """FP32 vectors with FP64 dot products: BiCGStab and GMRES on the config-1 operator reach
+    the FP64 oracle solution to FP32 accuracy."""
+    from paper_2604_22087_amd import fe
+    n, rve, P = _config1("f32")
+    eb = np.diag([0.01, 0.0, 0.0])
+    u0 = rve.affine_lift(eb)
+    r_e, k_e, _ = rve.element_residual_tangent(u0)
+    rhs = -assembly.assemble_vector(rve.conn, r_e, rve.n_dof) * rve.free
+    d = solver.matfree_diagonal(rve.conn, k_e, rve.n_dof, rve.mask)
+    x_ref, _, st, _ = solver.pcg(lambda x: solver.matfree_apply(rve.conn, k_e, x, rve.mask), d, rhs, 1e-13, 2000)
+    assert st == solver.OK
+    u = P.vector()
+    P.lift(eb, u, zero_free=True)
+    b = P.residual(u, apply_bc=True, store_tangent=True)
+    b.neg_()
+    x, res = P.pcg(b, op=fe.OP_MATFREE, rtol=1e-6, max_it=2000,
+                   solver=fe.SOLVER_BICGSTAB if solv == "bicgstab" else fe.SOLVER_GMRES)
+    print(f"  {solv} FP32: iterations {res.iterations}", flush=True)
+    assert res.status == 0
+    assert rel_err(x.double().cpu().numpy(), x_ref) <= 1e-4
+
+
 def test_surrogate_full_jacobian_with_bicgstab():
     import torch
     from paper_2604_22087_amd import fe
