@@ -11,11 +11,18 @@ Jacobi-PCG (diagonal from the CSR) to 1e-10.  Inputs are resident on the GPU
 before the timed region; each step restarts the ramp from zero.
 
 value = whole-step K*u throughput: dofs x operator applications / step time.
-The dominant kernel (the CG iteration's fused direction step + matrix-free K*u)
-is timed live with HIP events recorded by the library on the stream it runs on;
-its algorithmic bytes per launch are the compulsory traffic at the
-linearisation in force (r, M^-1, p_old read, p_new and A p written, phase ids,
-stored tangent values read).
+The dominant kernel (the single-reduction CG launch: vector updates, M^-1,
+matrix-free K*u and three dot products, one launch per iteration) is timed live
+with HIP events recorded by the library on the stream it runs on (every 16th
+launch of each solve); its algorithmic bytes per launch are the compulsory
+traffic at the linearisation in force (r, w, s, p, x, M^-1 read; r, s, p, x, w and
+the cleared next w written; phase ids; stored tangent values read).
+
+Further legs (outside the timed region, each recorded in its own entry): K*u
+rates of both operators, the FP32 ramp, the 96^3 surrogate against the return
+map, the assembled operator at 96^3 and 128^3, the plastic-path adjoint and the
+phase-modulus inverse problem at 64^3, the optional 128^3 Neo-Hookean leg, and
+the FP64 CPU oracle on a sample of the same workload.
 """
 from __future__ import annotations
 
