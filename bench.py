@@ -435,8 +435,8 @@ def main():
                                       f"{traffic['write_scale']:.3f} (1 GiB copy calibration), mean per launch over "
                                       f"{traffic['workload']}, where the algorithmic bytes are "
                                       f"{traffic['algorithmic_bytes_per_launch']:.4g}") if traffic else None,
-                     "kernel": "elem_kernel<double, OP_CG_APPLY, MS_J2> (CG direction step fused with the "
-                               "matrix-free K*u)",
+                     "kernel": "elem_kernel<double, OP_CG_APPLY, MS_J2> (single-reduction CG launch: vector "
+                               "updates, M^-1, matrix-free K*u and three dot products)",
                      "avg_launch_us": 1e3 * ku_avg_ms, "launches": cnt,
                      "sampling": f"HIP event pairs on operator launches 0, {CG_TIMING_STRIDE}, "
                                  f"{2 * CG_TIMING_STRIDE}, ... of every CG solve in the timed region",
