@@ -77,12 +77,15 @@ def test_path_gradient_finite_differences_fiber():
     picks = inputs.fd_element_picks(n ** 3, 6, seed=40)
     errs = []
     for e in picks:
-        h = 1e-4 * s[e]  # J carries ~1e-12 relative solve noise; truncation is ~(h/s)^2
+        # truncation is ~(h/s)^2; the quotient divides J's solve error by 2h, so the two
+        # evaluations solve to a Newton relative residual of 1e-14 instead of 1e-12 (at
+        # 1e-12, J's error over 2h reaches ~1e-6 of the gradient of a weak element)
+        h = 1e-4 * s[e]
         sp, sm = s.copy(), s.copy()
         sp[e] += h
         sm[e] -= h
-        jp, _, _ = _gpu(n, phase, sp, models, params, PATH)
-        jm, _, _ = _gpu(n, phase, sm, models, params, PATH)
+        jp, _, _ = _gpu(n, phase, sp, models, params, PATH, newton_rtol=1e-14)
+        jm, _, _ = _gpu(n, phase, sm, models, params, PATH, newton_rtol=1e-14)
         errs.append(abs((jp - jm) / (2 * h) - g[e]) / abs(g[e]))
     print(f"  FD vs adjoint: {np.array(errs)}", flush=True)
     assert max(errs) <= 1e-6
