@@ -549,83 +549,89 @@ __device__ __forceinline__ void cg_stage_brick(const ElemArgs& a, int n, int a0,
   const unsigned char* __restrict__ mask = a.mask;
   const bool blk = a.cg_block != 0, first = a.cg_j == 0;
   const int64_t np1 = n + 1;
-  int64_t dofs[STAGE_IT];
-  int cs[STAGE_IT];
-  bool in[STAGE_IT], own[STAGE_IT], fixed[STAGE_IT];
-  T ro[STAGE_IT][3], wo[STAGE_IT][3], so[STAGE_IT][3], m[STAGE_IT][3], po[STAGE_IT], xo[STAGE_IT], lv[STAGE_IT];
+  // loads in batches of SB rounds (all loads of a batch, then its updates and stores):
+  // FP64 takes all rounds at once, FP32 two batches, which measured faster there
+  constexpr int SB = sizeof(T) == 8 ? STAGE_IT : (STAGE_IT + 1) / 2;
 #pragma unroll
-  for (int t = 0; t < STAGE_IT; ++t) {
-    const int i = threadIdx.x + t * EBLOCK;
-    const int c = i % 3, nd = i / 3;
-    const int li = nd % NX, lj = (nd / NX) % NY, lk = nd / (NX * NY);
-    const int gi = a0 + li, gj = b0 + lj, gk = c0 + lk;
-    in[t] = i < NN * 3 && gi <= n && gj <= n && gk <= n;
-    own[t] = in[t] && (min(gi, n - 1) - a0 < TX) && (min(gj, n - 1) - b0 < TY) && (min(gk, n - 1) - c0 < TZ);
-    cs[t] = c;
-    const int64_t dof = in[t] ? 3 * (gi + np1 * (gj + np1 * gk)) + c : 0;
-    dofs[t] = dof;
-    const int64_t b3 = dof - c;
+  for (int t0 = 0; t0 < STAGE_IT; t0 += SB) {
+    int64_t dofs[SB];
+    int cs[SB];
+    bool in[SB], own[SB], fixed[SB];
+    T ro[SB][3], wo[SB][3], so[SB][3], m[SB][3], po[SB], xo[SB], lv[SB];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const bool need = in[t] && (blk || k == c);
-      ro[t][k] = need ? RO[b3 + k] : T(0);
-      wo[t][k] = need && !first ? WO[b3 + k] : T(0);
-      so[t][k] = need && !first ? SO[b3 + k] : T(0);
-    }
-    if (blk) {
-      const T* mb = M + 2 * b3;  // 6 entries per node: xx, yy, zz, yz, xz, xy
-      const int i0 = c == 0 ? 0 : (c == 1 ? 5 : 4), i1 = c == 0 ? 5 : (c == 1 ? 1 : 3),
-                i2 = c == 0 ? 4 : (c == 1 ? 3 : 2);
-      m[t][0] = in[t] ? mb[i0] : T(0);
-      m[t][1] = in[t] ? mb[i1] : T(0);
-      m[t][2] = in[t] ? mb[i2] : T(0);
-    } else {
-      m[t][0] = m[t][1] = m[t][2] = in[t] ? M[dof] : T(0);
-    }
-    fixed[t] = in[t] && mask && mask[dof];
-    po[t] = own[t] && !first ? P[dof] : T(0);
-    xo[t] = own[t] && !first ? X[dof] : T(0);
-    lv[t] = NEED_L && in[t] ? XL[dof] : T(0);
-  }
+    for (int t = 0; t < SB; ++t) {
+      const int i = threadIdx.x + (t0 + t) * EBLOCK;
+      const int c = i % 3, nd = i / 3;
+      const int li = nd % NX, lj = (nd / NX) % NY, lk = nd / (NX * NY);
+      const int gi = a0 + li, gj = b0 + lj, gk = c0 + lk;
+      in[t] = i < NN * 3 && gi <= n && gj <= n && gk <= n;
+      own[t] = in[t] && (min(gi, n - 1) - a0 < TX) && (min(gj, n - 1) - b0 < TY) && (min(gk, n - 1) - c0 < TZ);
+      cs[t] = c;
+      const int64_t dof = in[t] ? 3 * (gi + np1 * (gj + np1 * gk)) + c : 0;
+      dofs[t] = dof;
+      const int64_t b3 = dof - c;
 #pragma unroll
-  for (int t = 0; t < STAGE_IT; ++t) {
-    const int i = threadIdx.x + t * EBLOCK;
-    if (i >= NN * 3) break;
-    const int c = cs[t];
-    T rn[3], sn[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      sn[k] = wo[t][k] + beta * so[t][k];
-      rn[k] = first ? ro[t][k] : ro[t][k] - alpha * sn[k];
-    }
-    T u, uo;
-    if (blk) {
-      u = m[t][0] * rn[0] + m[t][1] * rn[1] + m[t][2] * rn[2];
-      uo = m[t][0] * ro[t][0] + m[t][1] * ro[t][1] + m[t][2] * ro[t][2];
-    } else {
-      u = m[t][0] * rn[c];
-      uo = m[t][0] * ro[t][c];
-    }
-    if (own[t]) {
-      const int64_t dof = dofs[t];
-      WZ[dof] = 0;
-      if (!first) {
-        const T pn = uo + beta * po[t];
-        P[dof] = pn;
-        X[dof] = xo[t] + alpha * pn;
-        SN[dof] = sn[c];
-        RN[dof] = rn[c];
+      for (int k = 0; k < 3; ++k) {
+        const bool need = in[t] && (blk || k == c);
+        ro[t][k] = need ? RO[b3 + k] : T(0);
+        wo[t][k] = need && !first ? WO[b3 + k] : T(0);
+        so[t][k] = need && !first ? SO[b3 + k] : T(0);
       }
-      g += (double)rn[c] * (double)u;
-      rr += (double)rn[c] * (double)rn[c];
+      if (blk) {
+        const T* mb = M + 2 * b3;  // 6 entries per node: xx, yy, zz, yz, xz, xy
+        const int i0 = c == 0 ? 0 : (c == 1 ? 5 : 4), i1 = c == 0 ? 5 : (c == 1 ? 1 : 3),
+                  i2 = c == 0 ? 4 : (c == 1 ? 3 : 2);
+        m[t][0] = in[t] ? mb[i0] : T(0);
+        m[t][1] = in[t] ? mb[i1] : T(0);
+        m[t][2] = in[t] ? mb[i2] : T(0);
+      } else {
+        m[t][0] = m[t][1] = m[t][2] = in[t] ? M[dof] : T(0);
+      }
+      fixed[t] = in[t] && mask && mask[dof];
+      po[t] = own[t] && !first ? P[dof] : T(0);
+      xo[t] = own[t] && !first ? X[dof] : T(0);
+      lv[t] = NEED_L && in[t] ? XL[dof] : T(0);
     }
-    if (fixed[t]) {
-      s_b[i] = u;
-      u = 0;
+#pragma unroll
+    for (int t = 0; t < SB; ++t) {
+      const int i = threadIdx.x + (t0 + t) * EBLOCK;
+      if (i >= NN * 3) break;
+      const int c = cs[t];
+      T rn[3], sn[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        sn[k] = wo[t][k] + beta * so[t][k];
+        rn[k] = first ? ro[t][k] : ro[t][k] - alpha * sn[k];
+      }
+      T u, uo;
+      if (blk) {
+        u = m[t][0] * rn[0] + m[t][1] * rn[1] + m[t][2] * rn[2];
+        uo = m[t][0] * ro[t][0] + m[t][1] * ro[t][1] + m[t][2] * ro[t][2];
+      } else {
+        u = m[t][0] * rn[c];
+        uo = m[t][0] * ro[t][c];
+      }
+      if (own[t]) {
+        const int64_t dof = dofs[t];
+        WZ[dof] = 0;
+        if (!first) {
+          const T pn = uo + beta * po[t];
+          P[dof] = pn;
+          X[dof] = xo[t] + alpha * pn;
+          SN[dof] = sn[c];
+          RN[dof] = rn[c];
+        }
+        g += (double)rn[c] * (double)u;
+        rr += (double)rn[c] * (double)rn[c];
+      }
+      if (fixed[t]) {
+        s_b[i] = u;
+        u = 0;
+      }
+      s_x[i] = in[t] ? u : T(0);
+      s_y[i] = 0;
+      if (NEED_L) s_l[i] = lv[t];
     }
-    s_x[i] = in[t] ? u : T(0);
-    s_y[i] = 0;
-    if (NEED_L) s_l[i] = lv[t];
   }
 }
 
