@@ -33,6 +33,9 @@ class Compliance(torch.autograd.Function):
         J = torch.dot(ub, R)
         ctx.save_for_backward(u, ub)
         ctx.problem, ctx.rtol = P, rtol
+        # the Problem may be given other materials or constraints before backward runs
+        # (e.g. a sum of objectives over several fields): keep the forward's own
+        ctx.field = (E.detach().clone(), phase, mask)
         ctx.info = info
         return J
 
@@ -40,6 +43,9 @@ class Compliance(torch.autograd.Function):
     def backward(ctx, gJ):
         u, ub = ctx.saved_tensors
         P = ctx.problem
+        E, phase, mask = ctx.field
+        P.set_materials(phase, [fe.LINEAR], [(1.0, 0.3)], E)
+        P.set_dirichlet(mask)
         rhs = P.residual(ub, apply_bc=True)     # P_f K u_b (linear: R(u_b) = K u_b)
         rhs.neg_()
         lam, res = P.pcg(rhs, op=fe.OP_MATFREE, rtol=ctx.rtol, max_it=200000)
@@ -99,6 +105,7 @@ class ReactionWorkPath(torch.autograd.Function):
         P.set_materials(phase, models, params, s.detach().contiguous())
         P.set_dirichlet(mask)
         ctx.problem, ctx.pcg_rtol, ctx.mask, ctx.path = P, pcg_rtol, mask, [np.asarray(e) for e in path]
+        ctx.field = (phase, list(models), list(params), s.detach().clone())
         ctx.newton_rtol, ctx.checkpoints = newton_rtol, checkpoints
         u, state = P.vector(), P.state()
         ctx.start = (u.clone(), state.clone())
@@ -165,6 +172,9 @@ class ReactionWorkPath(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gJ):
         P, ub = ctx.problem, ctx.ub
+        phase, models, params, s = ctx.field   # re-instate the forward's materials and constraints
+        P.set_materials(phase, models, params, s)
+        P.set_dirichlet(ctx.mask)
         grad = torch.zeros(P.n_el, dtype=ub.dtype, device=ub.device)
         ctx.adjoint_iterations, ctx.recompute_solves = [], 0
         if ctx.checkpoints is None:

@@ -98,3 +98,23 @@ def test_adjoint_fullsize_fd_and_euler():
     errs4, noise4 = fd_errors(1e-4, picks[:16])
     print(f"  FD (h=1e-4) on 16 elements: max {errs4.max():.2e}", flush=True)
     assert np.all(errs4 <= 1e-6 + 4 * noise4)
+
+
+def test_adjoint_two_objectives_share_one_problem():
+    """Two compliance objectives over different modulus fields on one Problem, summed and
+    differentiated together: each gradient must be the one of its own field (the backward
+    pass re-instates the materials its forward pass used)."""
+    import torch
+    from paper_2604_22087_amd.adjoint import compliance
+    n = 6
+    E1 = inputs.uniform_field(n ** 3, 1.0, 10.0, seed=4)
+    E2 = inputs.uniform_field(n ** 3, 1.0, 10.0, seed=5)
+    P, phase, mask, E1t = _torch_setup(n, E1)
+    E2t = torch.tensor(E2, device="cuda", requires_grad=True)
+    J = compliance(E1t, P, phase, mask, EB, rtol=1e-13) + compliance(E2t, P, phase, mask, EB, rtol=1e-13)
+    J.backward()
+    for E, Et in ((E1, E1t), (E2, E2t)):
+        rve = RVE(n, np.zeros(n ** 3, dtype=int), [phase_params("linear", 1.0, 0.3)], scale=E)
+        u_ref, _ = rve.solve_linear(EB, rtol=1e-14)
+        g_ref, _ = oadj.gradient(rve, u_ref)
+        assert rel_err(Et.grad.cpu().numpy(), g_ref) <= 1e-10
