@@ -32,20 +32,26 @@ def phase_params(model, E, nu, sigma_y=0.0, H=0.0):
 
 
 class RVE:
-    """Unit-cube RVE on an n^3 hex8 mesh with per-element phase and modulus scale."""
+    """Unit-cube RVE with per-element phase and modulus scale: the structured n^3 hex8
+    mesh, or any hex8 mesh given as mesh=(coords (n_nodes,3), conn (n_el,8))."""
 
-    def __init__(self, n, phase, phases, scale=None, elements=None):
+    def __init__(self, n, phase, phases, scale=None, elements=None, mesh=None):
         self.n = n
-        self.coords, conn = structured_hex8(n)
+        if mesh is None:
+            self.coords, conn = structured_hex8(n)
+        else:
+            self.coords = np.asarray(mesh[0], dtype=np.float64)
+            conn = np.asarray(mesh[1], dtype=np.int64)
+        n_el = len(conn)
         self.phase_all = np.asarray(phase, dtype=np.int64)
-        self.scale_all = np.ones(n ** 3) if scale is None else np.asarray(scale, dtype=np.float64)
+        self.scale_all = np.ones(n_el) if scale is None else np.asarray(scale, dtype=np.float64)
         # optional subset of elements (used to evaluate element quantities one by one)
-        self.elements = np.arange(n ** 3) if elements is None else np.asarray(elements)
+        self.elements = np.arange(n_el) if elements is None else np.asarray(elements)
         self.conn = conn[self.elements]
         self.phase = self.phase_all[self.elements]
         self.scale = self.scale_all[self.elements]
         self.phases = phases
-        self.n_dof = 3 * (n + 1) ** 3
+        self.n_dof = 3 * len(self.coords)
         self.mask = np.repeat(boundary_nodes(self.coords), 3).astype(np.uint8)
         self.free = 1.0 - self.mask
 
@@ -197,5 +203,6 @@ class RVE:
         return np.stack([w[q] * physical_gradients(xe, pts[q])[1] for q in range(8)], axis=1)
 
     def mean_stress(self, sigma_qp):
-        """Volume average of (n_el, 8, 6) stresses over the unit cube."""
-        return np.einsum("eq,eqi->i", self.qp_volumes(), sigma_qp)
+        """Volume average of (n_el, 8, 6) stresses: sum_q w detJ sigma_q / sum_q w detJ."""
+        v = self.qp_volumes()
+        return np.einsum("eq,eqi->i", v, sigma_qp) / v.sum()

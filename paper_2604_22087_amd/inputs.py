@@ -130,3 +130,95 @@ def glorot_uniform_params(layers=(13, 128, 128, 128, 6), seed: int = 5):
 def fd_element_picks(n_el: int, count: int = 64, seed: int = 40) -> np.ndarray:
     """Element ids for the finite-difference gradient check."""
     return np.sort(np.random.default_rng(seed).choice(n_el, count, replace=False))
+
+
+# ---- general (unstructured-numbered, distorted) hexahedral meshes of the unit cube ------------
+
+def _cube_rotations():
+    """The 24 proper rotations of the cube as 3x3 integer matrices."""
+    gens = [np.array([[0, -1, 0], [1, 0, 0], [0, 0, 1]]), np.array([[1, 0, 0], [0, 0, -1], [0, 1, 0]])]
+    found = [np.eye(3, dtype=np.int64)]
+    frontier = list(found)
+    while frontier:
+        nxt = []
+        for r in frontier:
+            for g in gens:
+                m = g @ r
+                if not any(np.array_equal(m, f) for f in found):
+                    found.append(m)
+                    nxt.append(m)
+        frontier = nxt
+    return found
+
+
+# corner offsets of the local node order (0,0,0) (1,0,0) (1,1,0) (0,1,0) (0,0,1) (1,0,1) (1,1,1) (0,1,1)
+LOCAL_CORNERS = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0],
+                          [0, 0, 1], [1, 0, 1], [1, 1, 1], [0, 1, 1]], dtype=np.int64)
+
+
+def distorted_cube_mesh(n: int, amplitude: float = 0.25, seed: int = 7, permute: bool = True):
+    """Hex8 mesh of [0,1]^3 with n elements per side, distorted and renumbered.
+
+    Starts from the n^3 grid; interior nodes move by U(-a h, a h) per component, face
+    nodes (not on an edge) within their face, edge nodes along their edge, corners stay
+    (a = amplitude), so the mesh still fills the unit cube exactly.  With permute: the
+    nodes and the elements are renumbered by random permutations, and each element's
+    local node order is one of the 24 proper rotations of the reference cube, drawn per
+    element (every local order stays right-handed).  All draws come from
+    default_rng(seed).  Returns (coords (n_nodes, 3) float64, conn (n_el, 8) int64 with
+    conn[e, p] = node of local node p).
+    """
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    idx = np.arange(n + 1)
+    kk, jj, ii = np.meshgrid(idx, idx, idx, indexing="ij")
+    grid = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)        # node (i,j,k), i fastest
+    coords = grid * h
+    on = (grid == 0) | (grid == n)                                        # per component: on a boundary plane
+    move = ~on                                                            # a component moves unless pinned
+    coords = coords + move * rng.uniform(-amplitude * h, amplitude * h, coords.shape)
+    a, b, c = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    base = np.stack([c.ravel(), b.ravel(), a.ravel()], axis=1)            # element (a,b,c), a fastest
+    corner = base[:, None, :] + LOCAL_CORNERS[None, :, :]                 # (n_el, 8, 3)
+    conn = corner[..., 0] + (n + 1) * (corner[..., 1] + (n + 1) * corner[..., 2])
+    if permute:
+        rots = _cube_rotations()
+        # local node p of the rotated element sits at corner R (s_p) of the original one
+        signs = 2 * LOCAL_CORNERS - 1
+        perms = []
+        for r in rots:
+            img = signs @ r.T
+            perms.append([int(np.flatnonzero((signs == v).all(axis=1))[0]) for v in img])
+        perms = np.array(perms)
+        pick = rng.integers(0, len(rots), len(conn))
+        conn = np.take_along_axis(conn, perms[pick], axis=1)
+        node_perm = rng.permutation(len(coords))                          # new id of old node
+        new_coords = np.empty_like(coords)
+        new_coords[node_perm] = coords
+        coords = new_coords
+        conn = node_perm[conn]
+        conn = conn[rng.permutation(len(conn))]
+    return coords, conn
+
+
+def mesh_centroids(coords, conn) -> np.ndarray:
+    """(n_el, 3) mean of each element's 8 node positions."""
+    return np.asarray(coords)[np.asarray(conn)].mean(axis=1)
+
+
+def sphere_phase_mesh(coords, conn, radius: float = 0.3, center=(0.5, 0.5, 0.5)) -> np.ndarray:
+    """Phase 1 where the element's node-mean centroid lies strictly within radius of center."""
+    d = mesh_centroids(coords, conn) - np.asarray(center, dtype=np.float64)
+    return (np.einsum("ij,ij->i", d, d) < radius * radius).astype(np.uint8)
+
+
+def boundary_dof_mask_mesh(coords, tol: float = 1e-12) -> np.ndarray:
+    """uint8 per dof: 1 for all three dofs of every node on a face of the unit cube."""
+    c = np.asarray(coords)
+    node = np.any((c < tol) | (c > 1.0 - tol), axis=1).astype(np.uint8)
+    return np.repeat(node, 3)
+
+
+def random_field_mesh(n_nodes: int, lo: float = -1e-3, hi: float = 1e-3, seed: int = 1) -> np.ndarray:
+    """U(lo, hi) on every dof of a mesh with n_nodes nodes."""
+    return np.random.default_rng(seed).uniform(lo, hi, 3 * n_nodes)
