@@ -21,7 +21,8 @@ the cleared next w written; phase ids; stored tangent values read).
 Further legs (outside the timed region, each recorded in its own entry): K*u
 rates of both operators, the FP32 ramp, the 96^3 surrogate against the return
 map, the assembled operator at 96^3 and 128^3, the plastic-path adjoint and the
-phase-modulus inverse problem at 64^3, the optional 128^3 Neo-Hookean leg, and
+phase-modulus inverse problem at 64^3, the 128^3 Neo-Hookean leg (FP32 element kernels
+with FP64 reductions against the FP64 run, with its own roofline), and
 the FP64 CPU oracle on a sample of the same workload.
 """
 from __future__ import annotations
@@ -47,6 +48,17 @@ MATRIX = (3.5, 0.35, 0.05, 0.1)
 # inside the timed region only every k-th CG operator launch carries an event pair (each
 # pair costs several microseconds of issue time, about 10% of a 64^3 iteration)
 CG_TIMING_STRIDE = 16
+
+# MI355X vector peaks (TFLOP/s): 256 CUs x 2.4 GHz; FP32 counts packed FMA, FP64 one FMA per lane
+VALU_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+
+# Algorithmic flops of one matrix-free Neo-Hookean K*x per element, for the kernel's own
+# algorithm: two sum-factorised gradients (x and the linearisation displacement: per component
+# and direction 4 nodal differences and a 2x2 -> 2x2 interpolation, 9 x 36 flops, plus 72 scalings
+# by 1/h), at each of 8 Gauss points the kinematics (traces, det H, J - 1, cofactors, 1/J,
+# log1p: 105 flops) and the linearised stress (F^-1 dH, its product with F^-1, the trace and the
+# combination: 160 flops), and the sum-factorised push-back (the transposed interpolation, 396).
+NH_APPLY_FLOPS_PER_ELEMENT = 2 * 396 + 8 * (105 + 160) + 396
 
 
 def measured_traffic():
@@ -167,11 +179,21 @@ def neohooke_leg(n):
         c, ms, by = P.profile_read()["matfree_apply"]
         P.profile(False)
         t = ms / max(c, 1) * 1e-3
+        flops = NH_APPLY_FLOPS_PER_ELEMENT * P.n_el
+        peak = VALU_PEAK_TFLOPS[prec]
         res[prec] = {"seconds": dt, "newton_iterations": info["newton_iterations"],
                      "pcg_iterations": info["pcg_iterations"], "ku_applies": info["operator_applies"],
+                     "line_search_halvings": info["line_search_halvings"],
                      "ku_us": 1e6 * t, "ku_gdofs": P.n_dof / t / 1e9, "ku_GBs": by / max(c, 1) / t / 1e9,
                      "ku_frac_hbm": by / max(c, 1) / t / 1e9 / HBM_PEAK_GBS,
-                     "whole_ramp_gdofs": P.n_dof * info["operator_applies"] / dt / 1e9}
+                     "whole_ramp_gdofs": P.n_dof * info["operator_applies"] / dt / 1e9,
+                     "roofline": {"bound": "alu", "achieved": flops / t / 1e12, "peak": peak, "unit": "TFLOP/s",
+                                  "frac": flops / t / 1e12 / peak, "traffic": None,
+                                  "kernel": f"elem_kernel<{'float' if prec == 'f32' else 'double'}, OP_CG_APPLY, "
+                                            f"MS_NH> (fused CG launch; F re-derived from the linearisation "
+                                            f"displacement at every Gauss point)",
+                                  "flops_per_launch": flops, "avg_launch_us": 1e6 * t, "launches": c,
+                                  "hbm_bytes_per_launch": by / max(c, 1)}}
         sol[prec] = (u.double(), np.array(sig))
         del P
     (u32, s32), (u64, s64) = sol["f32"], sol["f64"]
@@ -321,34 +343,51 @@ def csr_scaling_leg(sizes):
 
 
 def cpu_baseline(n, phase, gpu_info, path):
-    """The FP64 oracle on a bounded sample of the same workload (host cores)."""
+    """The FP64 oracle on a bounded sample of the same workload, on one host core with the BLAS
+    pool limited to one thread, extrapolated to one step.  One evaluation is repeated with the
+    BLAS pool at its default size: only BLAS calls inside the oracle are threaded, its einsum and
+    scatter loops run on one core either way."""
     from oracle import solver
     from oracle.rve import RVE, phase_params
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        cores = 1
+    from threadpoolctl import threadpool_info, threadpool_limits
+    pool = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     rve = RVE(n, phase, [phase_params("j2", *MATRIX), phase_params("linear", *FIBER)])
     samples = [0, len(path) // 2]  # the affine states of the first and a middle load step
-    t0 = time.perf_counter()
-    for k in samples:
-        r_e, k_e, _ = rve.element_residual_tangent(rve.affine_lift(path[k]), rve.zero_state())
-    t_rt = (time.perf_counter() - t0) / len(samples)
     x = np.random.default_rng(0).normal(size=rve.n_dof)
-    reps = 10
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        solver.matfree_apply(rve.conn, k_e, x, rve.mask)
-    t_apply = (time.perf_counter() - t0) / reps
-    applies, newton = gpu_info["operator_applies"], gpu_info["newton_iterations"] + len(path)
-    t_step = t_rt * newton + t_apply * applies
-    return {"value": rve.n_dof * applies / t_step / 1e9, "unit": "GDOF/s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"{len(samples)} residual+tangent evaluations ({t_rt:.1f} s each) and {reps} matrix-free K*u "
-                       f"({t_apply:.2f} s each) of the {n}^3 workload at the affine states of load steps "
-                       f"{', '.join(str(k + 1) for k in samples)}, scaled to the step's {newton} residual/tangent "
-                       f"evaluations and {applies} K*u"),
-            "qp_evals_per_s": 8 * rve.conn.shape[0] / t_rt, "step_seconds_est": t_step}
+    reps = 5
+
+    def sample(states):
+        t0 = time.perf_counter()
+        for k in states:
+            _, k_e, _ = rve.element_residual_tangent(rve.affine_lift(path[k]), rve.zero_state())
+        return (time.perf_counter() - t0) / len(states), k_e
+
+    # the step's work: one residual + tangent per Newton iteration and per load step (the
+    # predictor), one residual per line-search halving, one K*u per CG iteration
+    applies = gpu_info["operator_applies"]
+    n_rt = gpu_info["newton_iterations"] + len(path)
+    n_r = gpu_info["line_search_halvings"]
+    with threadpool_limits(limits=1):
+        t_rt, k_e = sample(samples)
+        t0 = time.perf_counter()
+        rve.element_residual_tangent(rve.affine_lift(path[samples[-1]]), rve.zero_state(), want_tangent=False)
+        t_r = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            solver.matfree_apply(rve.conn, k_e, x, rve.mask)
+        t_ku = (time.perf_counter() - t0) / reps
+    t_rt_pool, _ = sample(samples[:1])  # the same evaluation with the BLAS pool at its default size
+    step = t_rt * n_rt + t_r * n_r + t_ku * applies
+    return {"value": rve.n_dof * applies / step / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+            "extrapolated": True,
+            "sample": (f"{len(samples)} residual+tangent ({t_rt:.1f} s each), 1 residual-only ({t_r:.1f} s) and "
+                       f"{reps} matrix-free K*u ({t_ku:.2f} s each) evaluations of the {n}^3 workload at the affine "
+                       f"states of load steps {', '.join(str(k + 1) for k in samples)}, one thread, extrapolated "
+                       f"to the step's {n_rt} residual+tangent, {n_r} residual-only and {applies} K*u evaluations"),
+            "qp_evals_per_s": 8 * rve.conn.shape[0] / t_r, "step_seconds_est": step,
+            "blas_pool_check": {"blas_threads": int(pool), "residual_tangent_seconds": t_rt_pool,
+                                "note": "one residual+tangent evaluation with the BLAS pool at its default size: "
+                                        "the oracle's einsum and scatter loops run on one core either way"}}
 
 
 def _leg(fn, *args):
@@ -370,7 +409,7 @@ def main():
     ap.add_argument("--load-steps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 ramp")
-    ap.add_argument("--nh", type=int, default=0, help="also run the finite-strain Neo-Hookean leg at this n (0: skip)")
+    ap.add_argument("--nh", type=int, default=128, help="n of the finite-strain Neo-Hookean leg (0: skip)")
     ap.add_argument("--surrogate", type=int, default=96, help="n of the surrogate-vs-return-map leg (0: skip)")
     ap.add_argument("--adjoint-path", type=int, default=64, help="n of the plastic-path adjoint leg (0: skip)")
     ap.add_argument("--inverse", type=int, default=64, help="n of the inverse-problem leg (0: skip)")
