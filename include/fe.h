@@ -301,7 +301,7 @@ int fe_read_flags(fe_problem* p, int* flags_host, void* stream);
  * linear output.  Parameters are FP32 on the device, FE_MLP_PARAMS floats: for
  * layers l = 1..4 in order, the weights input-major Wt_l[in][out] followed by
  * the bias b_l[out].  Inputs/outputs are the normalised quantities. */
-enum { FE_MLP_IN = 13, FE_MLP_HIDDEN = 128, FE_MLP_OUT = 6, FE_MLP_PARAMS = 35590 };
+enum { FE_MLP_IN = 13, FE_MLP_HIDDEN = 128, FE_MLP_OUT = 6, FE_MLP_PARAMS = 35590, FE_MLP_STATIC_MAX = 8192 };
 
 /* y = net(x): x float [n][13], y float [n][6].  jac (float [n][6][6], may be
  * NULL): jac[s][o][j] = dy_o/dx_j for the first six inputs (forward-mode
@@ -314,6 +314,17 @@ int fe_mlp_forward(const float* W, const float* x, float* y, float* jac, float* 
  * work is scratch of float [n][3*128+6] (per-sample pre-activation gradients). */
 int fe_mlp_backward(const float* W, const float* x, const float* cache, const float* y, const float* target,
                     float* dW, double* loss_dev, float* work, int64_t n, void* stream);
+
+/* fe_mlp_backward without the workspace argument and without any device allocation, for
+ * callers that cannot allocate (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  The per-sample gradients go to a library-owned device array sized for
+ * FE_MLP_STATIC_MAX samples (12.8 MB, one copy per GPU the library runs on, held until the
+ * process ends).  n > FE_MLP_STATIC_MAX is FE_ERR_ARG.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (concurrent streams, threads) race and must be
+ * ordered by the caller.  Results equal fe_mlp_backward's up to the order of the FP32 atomic
+ * additions of the weight gradients. */
+int fe_mlp_backward_static(const float* W, const float* x, const float* cache, const float* y, const float* target,
+                           float* dW, double* loss_dev, int64_t n, void* stream);
 
 /* One Adam step (Kingma & Ba), t >= 1: m, v are the first/second moment buffers. */
 int fe_adam_step(float* W, const float* dW, float* m, float* v, int64_t n_param, double lr, double beta1,

@@ -8,6 +8,8 @@
 // consecutive floats).  The epilogue applies SiLU to value rows and scales the
 // tangent rows by SiLU'(z) of their sample's value row, fetched with a lane shuffle.
 // Training (backward pass, Adam) is lighter and runs on the vector units.
+#include <mutex>
+
 #include "fe_internal.hpp"
 
 namespace fe {
@@ -328,6 +330,66 @@ extern "C" int fe_mlp_backward(const float* W, const float* x, const float* cach
     set_error("fe_mlp_backward: all arrays are required, n > 0");
     return FE_ERR_ARG;
   }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(zero_kernel, dim3(64), dim3(256), 0, s, dW, (int64_t)FE_MLP_PARAMS, loss);
+  hipLaunchKernelGGL(mlp_delta_kernel, dim3((unsigned)((n + SB - 1) / SB)), dim3(256), 0, s, W, cache, y, target,
+                     work, loss, n);
+  hipLaunchKernelGGL(mlp_wgrad_kernel, dim3((unsigned)((n + WG_K - 1) / WG_K), 40), dim3(256), 0, s, x, cache, work,
+                     dW, n);
+  HIPCHK(hipGetLastError());
+  return FE_OK;
+}
+
+// Workspace of fe_mlp_backward_static: the per-sample pre-activation gradients of at most
+// FE_MLP_STATIC_MAX samples, in a file-scope device array (each GPU the library runs on holds its
+// own copy, 12.8 MB, until the process ends).  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol): the device address is looked up
+// once per device with hipGetSymbolAddress and kept in g_scratch_dev.
+static __device__ __align__(256) float scratch[(size_t)FE_MLP_STATIC_MAX * WSTRIDE];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch_dev[SCRATCH_MAX_DEVICES];
+
+// Device address of `scratch` on the current device, or null (error recorded) on failure.
+static float* scratch_on_current_device() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    hip_fail(e, "hipGetDevice");
+    return nullptr;
+  }
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) {
+    set_error("fe_mlp_backward_static: device index beyond the supported range");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+      return nullptr;
+    }
+    g_scratch_dev[dev] = static_cast<float*>(ptr);
+  }
+  return g_scratch_dev[dev];
+}
+
+extern "C" int fe_mlp_backward_static(const float* W, const float* x, const float* cache, const float* y,
+                                      const float* target, float* dW, double* loss, int64_t n, void* stream) {
+  if (!W || !x || !cache || !y || !target || !dW || !loss || n <= 0) {
+    set_error("fe_mlp_backward_static: all arrays are required, n > 0");
+    return FE_ERR_ARG;
+  }
+  if (n > FE_MLP_STATIC_MAX) {
+    set_error("fe_mlp_backward_static: n exceeds FE_MLP_STATIC_MAX samples (use fe_mlp_backward with a workspace)");
+    return FE_ERR_ARG;
+  }
+  float* work = scratch_on_current_device();
+  if (!work) return FE_ERR_HIP;
+  // the delta kernel writes every workspace entry the weight-gradient kernel reads
+  // (rows 0..n-1), so the array's contents from an earlier call never matter
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(zero_kernel, dim3(64), dim3(256), 0, s, dW, (int64_t)FE_MLP_PARAMS, loss);
   hipLaunchKernelGGL(mlp_delta_kernel, dim3((unsigned)((n + SB - 1) / SB)), dim3(256), 0, s, W, cache, y, target,

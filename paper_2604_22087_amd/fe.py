@@ -78,6 +78,7 @@ SIGNATURES = [
     ("fe_linearization_stats", _i32, [_vp, ctypes.POINTER(_i64), _vp]),
     ("fe_mlp_forward", _i32, [_vp, _vp, _vp, _vp, _vp, _i64, _vp]),
     ("fe_mlp_backward", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp]),
+    ("fe_mlp_backward_static", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp]),
     ("fe_set_surrogate", _i32, [_vp, _vp, _dbl]),
     ("fe_surrogate_stats", _i32, [_vp, ctypes.POINTER(_i64), _vp]),
     ("fe_set_capture", _i32, [_vp, _vp, _vp, _i64, _vp, _i32]),
@@ -416,6 +417,23 @@ def mlp_backward(W, x, cache, y, target):
     work = torch.empty(n, 3 * MLP_HIDDEN + MLP_OUT, dtype=torch.float32, device=x.device)
     _check(lib.fe_mlp_backward(_ptr(W), _ptr(x), _ptr(cache), _ptr(y), _ptr(target), _ptr(dW), _ptr(loss),
                                _ptr(work), n, _stream()), "fe_mlp_backward")
+    return dW, loss
+
+
+MLP_STATIC_MAX = 8192
+
+
+def mlp_backward_static(W, x, cache, y, target, dW=None, loss=None):
+    """mlp_backward through the entry point that allocates nothing (library-owned workspace,
+    n <= MLP_STATIC_MAX); dW and loss may be given to keep the call allocation-free here too."""
+    lib = load_library()
+    n = x.shape[0]
+    if dW is None:
+        dW = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device=x.device)
+    _check(lib.fe_mlp_backward_static(_ptr(W), _ptr(x), _ptr(cache), _ptr(y), _ptr(target), _ptr(dW), _ptr(loss),
+                                      n, _stream()), "fe_mlp_backward_static")
     return dW, loss
 
 
