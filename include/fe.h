@@ -2,8 +2,9 @@
  * fe.h -- C ABI of the MI355X element-level finite-element hot path.
  *
  * The library computes, for a two-phase (or multi-phase) micromechanics RVE on
- * a structured n x n x n mesh of 8-node bricks covering the unit cube, the
- * pieces of the paper's Newton method for R(u) = 0 (Sec. II-A):
+ * a structured n x n x n mesh of 8-node bricks covering the unit cube, or on any
+ * conforming mesh of 8-node bricks (fe_problem_create_hex8), the pieces of the
+ * paper's Newton method for R(u) = 0 (Sec. II-A):
  *   - element residuals assembled into R(u)            (fe_residual)
  *   - element Jacobians assembled into a sparse K(u)   (fe_csr_indices, fe_tangent_csr;
  *     the sorted, duplicate-combined sparse tuple of Sec. III-B)
@@ -14,9 +15,10 @@
  *   - the vector-Jacobian product of the residual with respect to a per-element
  *     modulus scale, for adjoint gradients               (fe_vjp)
  *
- * Mesh conventions (fixed): node (i,j,k) has id i + (n+1)(j + (n+1)k) at
- * x = (i,j,k)/n; element (a,b,c) has id a + n(b + nc); dof = 3*node + comp.
- * 2x2x2 Gauss points, point q = qx + 2 qy + 4 qz.
+ * Mesh conventions of the structured problem: node (i,j,k) has id
+ * i + (n+1)(j + (n+1)k) at x = (i,j,k)/n; element (a,b,c) has id a + n(b + nc).
+ * Both kinds: dof = 3*node + comp; 2x2x2 Gauss points, point q = qx + 2 qy + 4 qz
+ * at reference coordinates (+-1/sqrt 3) with weight 1.
  *
  * Conventions of every call:
  *   - Array arguments are DEVICE pointers unless the name ends in _host.  The
@@ -100,11 +102,42 @@ typedef struct {
 /* Create the structured problem: n elements per side of [0,1]^3 (1 <= n <= 1024,
  * with 3(n+1)^3 dofs and 9(3n+1)^3 matrix entries both below 2^31), precision
  * FE_F64 or FE_F32, on the current HIP device.  *out receives an opaque handle
- * owned by the library (free with fe_problem_destroy). */
+ * owned by the library (free with fe_problem_destroy).  This is the problem
+ * structure of the paper's construction phase (Fig. 1: mesh, element information,
+ * Dirichlet data; Sec. IV) for the regular RVE meshes of Sec. V-A, whose numbering
+ * (above) lets the element kernels stage bricks of elements and the sparse pattern
+ * be written in closed form. */
 int fe_problem_create(fe_problem** out, int n, int precision);
+
+/* Create a problem on a general mesh of 8-node bricks (the element information and
+ * problem structure of Fig. 1 given explicitly; Sec. III-B builds the Jacobian of
+ * such a mesh by sorting and combining the element pairs, Sec. IV).
+ *   coords: double, DEVICE, [3][n_nodes] (x of all nodes, then y, then z);
+ *   conn:   int32, DEVICE, [8][n_el]: conn[p * n_el + e] = node of local node p of
+ *           element e, local order (-1,-1,-1) (1,-1,-1) (1,1,-1) (-1,1,-1) (-1,-1,1)
+ *           (1,-1,1) (1,1,1) (-1,1,1) in reference coordinates (any right-handed
+ *           numbering of the brick, e.g. a rotation of this one).
+ * Both are copied (the caller keeps ownership; coordinates are stored in the
+ * problem's precision).  The library checks every node id (FE_ERR_ARG outside
+ * [0, n_nodes)) and det J > 0 at every Gauss point (FE_ERR_ARG otherwise), then builds
+ * the node-pair pattern on the device: every element's 64 (row node, column node)
+ * pairs are bucketed by row and sorted by (column, element), duplicates combined;
+ * the sorted element list of each pair drives the deterministic gather of
+ * fe_tangent_csr.  Limits: 3 n_nodes < 2^31, 64 n_el < 2^31, 9 (node pairs) < 2^31,
+ * at most 128 elements per node (FE_ERR_ARG otherwise).  Every other call works as on
+ * the structured problem (dofs 3 node + c, Gauss point q of element e at index
+ * q n_el + e of state arrays, fe_lift from the stored coordinates, fe_mean_stress
+ * divided by the mesh volume), except: FE_PC_ILU0, the learned surrogate and its
+ * sample capture, and fe_vjp_path are structured-only (FE_ERR_ARG); CG runs one
+ * operator, one update and one direction launch per iteration.  Synchronises the
+ * stream.  Needs device memory of 64 n_el + 12 (node pairs) + 3 n_nodes int32 and,
+ * once fe_tangent_csr runs, 576 n_el reals for the element Jacobians. */
+int fe_problem_create_hex8(fe_problem** out, int64_t n_nodes, int64_t n_el, const double* coords,
+                           const int32_t* conn, int precision, void* stream);
 void fe_problem_destroy(fe_problem* p);
 
-/* Sizes: out_host[0..5] = n, n_el, n_nodes, n_dof, n_qp (= 8 n_el), nnz. */
+/* Sizes: out_host[0..5] = n (0 for a general mesh), n_el, n_nodes, n_dof,
+ * n_qp (= 8 n_el), nnz. */
 int fe_problem_sizes(const fe_problem* p, int64_t* out_host);
 
 /* Materials (the phase-dependent laws of Sec. V-A).  phase: uint8 [n_el] with
@@ -115,10 +148,13 @@ int fe_problem_sizes(const fe_problem* p, int64_t* out_host);
 int fe_set_materials(fe_problem* p, const uint8_t* phase, int n_phases, const int* models_host,
                      const double* params_host, const void* scale, void* stream);
 
-/* Dirichlet dofs: uint8 [n_dof], 1 = constrained (copied).  Default: none. */
+/* Dirichlet dofs (the boundary treatment that Sec. II-B applies before the solve):
+ * uint8 [n_dof], 1 = constrained (copied into library memory).  Default: none.
+ * mask = NULL removes them. */
 int fe_set_dirichlet(fe_problem* p, const uint8_t* mask, void* stream);
 
-/* u[d] = (eps_bar . x)_comp on constrained dofs d; free dofs keep their value
+/* Affine boundary values of a macro strain (the RVE loading of Sec. V-A):
+ * u[d] = (eps_bar . x)_comp on constrained dofs d; free dofs keep their value
  * (zero_free = 0) or are set to 0 (zero_free = 1).  eps_bar_host: 3x3 row-major. */
 int fe_lift(fe_problem* p, const double* eps_bar_host, void* u, int zero_free, void* stream);
 
@@ -131,8 +167,10 @@ int fe_lift(fe_problem* p, const double* eps_bar_host, void* u, int zero_free, v
 int fe_residual(fe_problem* p, const void* u, const void* state_in, void* state_out, void* r,
                 int flags, void* stream);
 
-/* Number of stored entries of the sparse Jacobian (structural pattern: every
- * pair of dofs that share an element, explicit zeros kept): 9(3n+1)^3. */
+/* Number of stored entries of the sparse Jacobian, known before any value is
+ * computed (the pre-computed non-zero count of the assembly listing in Sec. III-B;
+ * structural pattern: every pair of dofs that share an element, explicit zeros
+ * kept): 9(3n+1)^3 on the structured mesh, 9 x (node pairs) on a general one. */
 int fe_csr_nnz(const fe_problem* p, int64_t* nnz_host);
 
 /* CSR pattern, rows = dofs, columns ascending: row_ptr int32 [n_dof+1],
@@ -162,7 +200,9 @@ int fe_apply_csr(fe_problem* p, const int32_t* row_ptr, const int32_t* col_idx, 
 int fe_apply_csr_nodal(fe_problem* p, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
                        const void* x, void* y, void* stream);
 
-/* Diagonal of the (masked, if apply_bc) matrix-free operator: d real [n_dof]. */
+/* Diagonal of the (masked, if apply_bc) matrix-free operator, the Jacobi
+ * preconditioner of the Krylov solves compared in Fig. 4: d real [n_dof]
+ * (constrained dofs get 1 when apply_bc). */
 int fe_diagonal(fe_problem* p, void* d, int apply_bc, void* stream);
 
 /* Preconditioner of fe_pcg and fe_newton's inner solves (default FE_PC_JACOBI).
@@ -260,6 +300,13 @@ int fe_vjp_path(fe_problem* p, const void* u, const void* state_in, const void* 
 int fe_newton(fe_problem* p, const double* load_path_host, int n_steps, const fe_newton_opts* opts,
               void* u, void* state, double* sigma_bar_host, fe_newton_info* info_host,
               void* stream);
+
+/* Commit the plastic history of a converged load step (the state update that ends
+ * each Newton solve of Sec. II-A / V-A): state = state_trial, both real [7][8][n_el]
+ * (the trial state written by fe_residual's state_out).  For callers that drive
+ * their own Newton loop; fe_newton commits by itself.  No-op for problems without
+ * J2 phases.  Enqueued on the stream (a copy kernel, no allocation). */
+int fe_commit_state(fe_problem* p, const void* state_trial, void* state, void* stream);
 
 /* Volume-averaged stress (1/V) sum_q w_q detJ_q sigma_q at (u, state_in),
  * written to sigma_host[6] in Voigt order [xx,yy,zz,yz,xz,xy]. */

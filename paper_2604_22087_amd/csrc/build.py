@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
-SOURCES = ["fe_kernels.hip", "fe_mlp.hip", "fe_krylov.hip", "fe_ilu.hip", "fe_api.hip"]
+SOURCES = ["fe_kernels.hip", "fe_general.hip", "fe_mlp.hip", "fe_krylov.hip", "fe_ilu.hip", "fe_api.hip"]
 OUT = os.path.join(PKG, "libfe.so")
 
 FLAGS = [

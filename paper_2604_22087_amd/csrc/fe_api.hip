@@ -161,29 +161,28 @@ void fe_problem_destroy(fe_problem* p) {
   free_dev(p->sur_jac);
   free_dev(p->sur_D);
   free_dev(p->sur_count);
+  free_dev(p->coords);
+  free_dev(p->conn);
+  free_dev(p->adj_ptr);
+  free_dev(p->adj);
+  free_dev(p->pair_row);
+  free_dev(p->pair_src_ptr);
+  free_dev(p->pair_src);
+  free_dev(p->gen_col);
+  free_dev(p->ke);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->host_ctrl) (void)hipHostFree(p->host_ctrl);
   if (p->host_buf) (void)hipHostFree(p->host_buf);
   delete p;
 }
 
-int fe_problem_create(fe_problem** out, int n, int precision) {
-  if (!out) return arg_error("out is null");
-  *out = nullptr;
-  if (n < 1 || n > 1024) return arg_error("n must be in [1, 1024]");
-  if (precision != FE_F64 && precision != FE_F32) return arg_error("precision must be FE_F64 or FE_F32");
-  const int64_t np1 = n + 1;
-  if (3 * np1 * np1 * np1 >= (int64_t(1) << 31)) return arg_error("too many dofs for 32-bit indexing");
-  fe_problem* p = new fe_problem();
-  p->n = n;
-  p->prec = precision;
-  p->n_el = (int64_t)n * n * n;
-  p->n_nodes = np1 * np1 * np1;
-  p->n_dof = 3 * p->n_nodes;
-  const int64_t t = 3 * (int64_t)n + 1;
-  p->nnz = 9 * t * t * t;
-  p->h = 1.0 / n;
-  HIPCHK(hipGetDevice(&p->device));
+// Library memory every problem needs (vectors, partial sums, scalars, flags); destroys p on failure.
+static int alloc_common(fe_problem* p) {
+  if (hipError_t e0 = hipGetDevice(&p->device)) {
+    fe_problem_destroy(p);
+    return hip_fail(e0, "hipGetDevice");
+  }
+  const int n = p->n;
   const size_t rs = real_size(p), vec = rs * p->n_dof;
   int st = FE_OK;
   const size_t n_part =
@@ -208,6 +207,121 @@ int fe_problem_create(fe_problem** out, int n, int precision) {
   // default material: one linear phase with E = 1, nu = 0.3
   p->mat.n = 1;
   p->mat.ph[0] = PhaseConst{FE_LINEAR, 1.0 * 0.3 / (1.3 * 0.4), 1.0 / 2.6, 1.0 / 1.2, 1.0 / 2.6, 0, 0};
+  return FE_OK;
+}
+
+int fe_problem_create(fe_problem** out, int n, int precision) {
+  if (!out) return arg_error("out is null");
+  *out = nullptr;
+  if (n < 1 || n > 1024) return arg_error("n must be in [1, 1024]");
+  if (precision != FE_F64 && precision != FE_F32) return arg_error("precision must be FE_F64 or FE_F32");
+  const int64_t np1 = n + 1;
+  if (3 * np1 * np1 * np1 >= (int64_t(1) << 31)) return arg_error("too many dofs for 32-bit indexing");
+  fe_problem* p = new fe_problem();
+  p->n = n;
+  p->prec = precision;
+  p->n_el = (int64_t)n * n * n;
+  p->n_nodes = np1 * np1 * np1;
+  p->n_dof = 3 * p->n_nodes;
+  const int64_t t = 3 * (int64_t)n + 1;
+  p->nnz = 9 * t * t * t;
+  p->h = 1.0 / n;
+  if (int st = alloc_common(p)) return st;
+  *out = p;
+  return FE_OK;
+}
+
+int fe_problem_create_hex8(fe_problem** out, int64_t n_nodes, int64_t n_el, const double* coords,
+                           const int32_t* conn, int precision, void* stream) {
+  if (!out) return arg_error("out is null");
+  *out = nullptr;
+  if (!coords || !conn) return arg_error("coords and conn are required");
+  if (n_nodes < 8 || n_el < 1) return arg_error("a mesh needs at least 8 nodes and one element");
+  if (precision != FE_F64 && precision != FE_F32) return arg_error("precision must be FE_F64 or FE_F32");
+  if (3 * n_nodes >= (int64_t(1) << 31)) return arg_error("too many dofs for 32-bit indexing");
+  if (64 * n_el >= (int64_t(1) << 31)) return arg_error("too many elements for 32-bit element-pair codes");
+  hipStream_t s = S(stream);
+  fe_problem* p = new fe_problem();
+  p->general = true;
+  p->n = 0;
+  p->prec = precision;
+  p->n_el = n_el;
+  p->n_nodes = n_nodes;
+  p->n_dof = 3 * n_nodes;
+  p->h = 0.0;
+  if (int st = alloc_common(p)) return st;
+  const size_t rs = real_size(p);
+  int32_t *cnt = nullptr, *coo_ptr = nullptr, *cursor = nullptr, *tmp = nullptr;
+  auto fail = [&](int st) {
+    free_dev(cnt);
+    free_dev(coo_ptr);
+    free_dev(cursor);
+    free_dev(tmp);
+    fe_problem_destroy(p);
+    return st;
+  };
+  const int64_t tmp_words = gen_scan_tmp_words(n_nodes);
+  int st;
+  if ((st = alloc(&p->coords, rs * 3 * n_nodes)) || (st = alloc((void**)&p->conn, sizeof(int32_t) * 8 * n_el)) ||
+      (st = alloc((void**)&p->adj_ptr, sizeof(int32_t) * (n_nodes + 1))) ||
+      (st = alloc((void**)&p->pair_src, sizeof(int32_t) * 64 * n_el)) ||
+      (st = alloc((void**)&p->gen_col, sizeof(int32_t) * 64 * n_el)) ||
+      (st = alloc((void**)&cnt, sizeof(int32_t) * n_nodes)) ||
+      (st = alloc((void**)&coo_ptr, sizeof(int32_t) * (n_nodes + 1))) ||
+      (st = alloc((void**)&cursor, sizeof(int32_t) * n_nodes)) ||
+      (st = alloc((void**)&tmp, sizeof(int32_t) * tmp_words)))
+    return fail(st);
+  hipError_t e;
+  int bad = 0;
+  // copies, node ids in range
+  if ((e = gen_setup(p, coords, conn, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(&bad, p->flags, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return fail(hip_fail(e, "fe_problem_create_hex8"));
+  if (bad) {
+    fail(FE_OK);
+    return arg_error("connectivity holds a node id outside [0, n_nodes)");
+  }
+  // every Gauss point of every element must have det J > 0 (right-handed, not degenerate)
+  double vol = 0;
+  if ((e = hipMemsetAsync(p->stress_sum, 0, sizeof(double), s)) != hipSuccess ||
+      (e = gen_check_geometry(p, p->stress_sum, p->flags, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(&vol, p->stress_sum, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(&bad, p->flags, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipMemsetAsync(p->flags, 0, sizeof(int), s)) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess)
+    return fail(hip_fail(e, "fe_problem_create_hex8"));
+  if (bad) {
+    fail(FE_OK);
+    return arg_error("an element has det J <= 0 at a Gauss point (inverted, degenerate or left-handed node order)");
+  }
+  p->volume = vol;
+  // sorted node-pair pattern
+  int64_t n_pairs = 0;
+  int max_row = 0;
+  if ((e = gen_symbolic(p, cnt, coo_ptr, cursor, tmp, s, &n_pairs, &max_row)) != hipSuccess)
+    return fail(hip_fail(e, "fe_problem_create_hex8 (symbolic)"));
+  if (max_row > 1024) {
+    fail(FE_OK);
+    return arg_error("a node is shared by more than 128 elements");
+  }
+  if (9 * n_pairs >= (int64_t(1) << 31)) {
+    fail(FE_OK);
+    return arg_error("matrix too large for int32 CSR indices");
+  }
+  p->n_pairs = n_pairs;
+  p->nnz = 9 * n_pairs;
+  if ((st = alloc((void**)&p->adj, sizeof(int32_t) * n_pairs)) ||
+      (st = alloc((void**)&p->pair_row, sizeof(int32_t) * n_pairs)) ||
+      (st = alloc((void**)&p->pair_src_ptr, sizeof(int32_t) * (n_pairs + 1))))
+    return fail(st);
+  if ((e = gen_pairs(p, coo_ptr, s)) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess)
+    return fail(hip_fail(e, "fe_problem_create_hex8 (pairs)"));
+  free_dev(cnt);
+  free_dev(coo_ptr);
+  free_dev(cursor);
+  free_dev(tmp);
+  free_dev(p->gen_col);
+  p->gen_col = nullptr;
   *out = p;
   return FE_OK;
 }
@@ -413,7 +527,15 @@ int fe_mean_stress(fe_problem* p, const void* u, const void* state_in, double* s
   if (st) return st;
   HIPCHK(hipMemcpyAsync(p->host_buf, p->stress_sum, 6 * sizeof(double), hipMemcpyDeviceToHost, S(stream)));
   HIPCHK(hipStreamSynchronize(S(stream)));
-  for (int k = 0; k < 6; ++k) sigma[k] = p->host_buf[k];  // unit-cube volume
+  for (int k = 0; k < 6; ++k) sigma[k] = p->host_buf[k] / p->volume;
+  return FE_OK;
+}
+
+int fe_commit_state(fe_problem* p, const void* state_trial, void* state, void* stream) {
+  CHKP(p);
+  if (!state_trial || !state) return arg_error("state_trial and state are required");
+  if (p->model_set != MS_J2) return FE_OK;  // only J2 points carry history
+  HIPCHK(gen_copy_state(p, state_trial, state, 7 * 8 * p->n_el, S(stream)));
   return FE_OK;
 }
 
@@ -437,10 +559,18 @@ int fe_csr_indices(fe_problem* p, int32_t* row_ptr, int32_t* col_idx, void* stre
   return FE_OK;
 }
 
+// General meshes keep every element's dense Jacobian between the matrix-core kernel and the
+// sorted gather into the CSR values: n_el x 576 reals, allocated on the first tangent.
+static int ensure_ke(fe_problem* p) {
+  if (!p->general || p->ke) return FE_OK;
+  return alloc(&p->ke, real_size(p) * 576 * (size_t)p->n_el);
+}
+
 int fe_tangent_csr(fe_problem* p, const void* u, const void* state_in, void* vals, int apply_bc, void* stream) {
   CHKP(p);
   if (!u || !vals) return arg_error("u and vals are required");
   if (int st = check_csr_size(p)) return st;
+  if (int st = ensure_ke(p)) return st;
   if (p->model_set != MS_LINEAR) {
     int st = residual_impl(p, u, state_in, nullptr, nullptr, FE_STORE_TANGENT, nullptr, S(stream));
     if (st) return st;
@@ -518,6 +648,8 @@ int fe_set_preconditioner(fe_problem* p, int kind) {
   CHKP(p);
   if (kind != FE_PC_JACOBI && kind != FE_PC_BLOCK_JACOBI && kind != FE_PC_ILU0)
     return arg_error("kind must be FE_PC_JACOBI, FE_PC_BLOCK_JACOBI or FE_PC_ILU0");
+  if (kind == FE_PC_ILU0 && p->general)
+    return arg_error("FE_PC_ILU0 orders nodes by the parities of structured grid indices: not on a general mesh");
   if (kind == FE_PC_BLOCK_JACOBI && !p->w_blk) {
     if (int st = alloc(&p->w_blk, 6 * real_size(p) * (size_t)p->n_nodes)) return st;
   }
@@ -620,7 +752,7 @@ static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, 
   } else {
     HIPCHK(launch_diag(p, p->w_d, 1, s));
   }
-  const bool fused = op == FE_OP_MATFREE;
+  const bool fused = op == FE_OP_MATFREE && !p->general;
   if (fused) {
     if (!p->w_cg && alloc(&p->w_cg, 6 * real_size(p) * (size_t)p->n_dof)) return FE_ERR_OOM;
     HIPCHK(cgs_init(p, b, x, rtol, max_it, s));
@@ -934,6 +1066,7 @@ extern "C" int fe_vjp_path(fe_problem* p, const void* u, const void* state_in, c
                            void* mu_out, void* u_bar, void* s_bar, void* stream) {
   CHKP(p);
   if (p->prec != FE_F64) return arg_error("fe_vjp_path needs an FE_F64 problem");
+  if (p->general) return arg_error("fe_vjp_path runs on structured problems only");
   if (!p->materials_set) return arg_error("materials not set");
   if (p->model_set == MS_NH) return arg_error("fe_vjp_path supports linear and J2 phases only");
   if (!u || !mu_out) return arg_error("u and mu_out are required");
@@ -984,6 +1117,7 @@ extern "C" int fe_newton(fe_problem* p, const double* path, int n_steps, const f
         return FE_ERR_OOM;
       HIPCHK(launch_csr_pattern(p, p->csr_rp, p->csr_ci, s));
     }
+    if (int st = ensure_ke(p)) return st;
   }
   fe_newton_info inf{};
   inf.status = FE_OK;
@@ -1073,7 +1207,7 @@ extern "C" int fe_newton(fe_problem* p, const double* path, int n_steps, const f
       int st = fe_mean_stress(p, u, state, sigma_bar + 6 * step, stream);
       if (st) return st;
     }
-    if (trial) HIPCHK(hipMemcpyAsync(state, trial, rs * 7 * 8 * p->n_el, hipMemcpyDeviceToDevice, s));
+    if (trial) HIPCHK(gen_copy_state(p, trial, state, 7 * 8 * p->n_el, s));
     inf.steps_done += 1;
   }
   HIPCHK(hipStreamSynchronize(s));
@@ -1127,6 +1261,8 @@ static int operator_bytes(fe_problem* p, int op, hipStream_t s, double* bytes) {
   }
   // x in, y out, phase ids, and per J2 point the plastic flag word plus 5 more values if plastic
   double b = 2.0 * w * (double)p->n_dof + (double)p->n_el + w * ((double)st[0] + 5.0 * (double)st[1]);
+  if (p->general)  // connectivity and coordinates; all six tangent words of every J2 point
+    b = 2.0 * w * (double)p->n_dof + 33.0 * (double)p->n_el + 3.0 * w * (double)p->n_nodes + 6.0 * w * (double)st[0];
   if (p->model_set == MS_NH) b += w * (double)p->n_dof;  // linearisation point gathered as well
   *bytes = b;
   return FE_OK;
@@ -1150,6 +1286,7 @@ extern "C" int fe_linearization_stats(fe_problem* p, int64_t* out, void* stream)
 
 extern "C" int fe_set_surrogate(fe_problem* p, const float* W, double tol) {
   CHKP(p);
+  if (W && p->general) return arg_error("the surrogate runs on structured problems only");
   if (!W) {
     p->sur_W = nullptr;
     return FE_OK;
@@ -1196,6 +1333,7 @@ extern "C" int fe_surrogate_stats(fe_problem* p, int64_t* out, void* stream) {
 
 extern "C" int fe_set_capture(fe_problem* p, float* x, float* y, int64_t capacity, unsigned int* count, int stride) {
   CHKP(p);
+  if (x && p->general) return arg_error("sample capture runs on structured problems only");
   if (!x) {
     p->cap_x = nullptr;
     return FE_OK;

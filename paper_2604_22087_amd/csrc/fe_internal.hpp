@@ -89,6 +89,8 @@ enum GmStage { GM_START = 1, GM_BASIS, GM_ORTHO, GM_FINISH, GM_RESIDUAL, GM_ADD_
 
 // single-reduction CG: slots per reduced quantity that the workgroups of a launch add into
 constexpr int CGS_SLOTS = 256;
+// general meshes: workgroups (= partial slots) of the pass that completes the CG operator
+constexpr int GEN_CG_GRID = 512;
 
 struct CgCtrl {
   double rz[2];     // r.M^-1 r after update k-1, slot k&1 (written by the direction step of iteration k)
@@ -242,6 +244,19 @@ struct fe_problem {
   std::vector<std::pair<int, size_t>> prof_recs;  // (kernel class, index of the start event)
   size_t ev_used = 0;
   double prof_bytes[5] = {0, 0, 0, 0, 0};         // algorithmic bytes of the recorded launches
+  // general hex8 mesh (fe_problem_create_hex8; n = 0 there)
+  bool general = false;
+  double volume = 1.0;             // sum over Gauss points of w detJ (the unit cube: 1)
+  void* coords = nullptr;          // real [3][n_nodes]
+  int32_t* conn = nullptr;         // [8][n_el]
+  int64_t n_pairs = 0;             // node pairs that share an element (nnz = 9 n_pairs)
+  int32_t* adj_ptr = nullptr;      // [n_nodes + 1] first pair of each row node
+  int32_t* adj = nullptr;          // [n_pairs] column node of each pair, ascending within a row
+  int32_t* pair_row = nullptr;     // [n_pairs] row node of each pair
+  int32_t* pair_src_ptr = nullptr; // [n_pairs + 1] run of each pair in pair_src
+  int32_t* pair_src = nullptr;     // [64 n_el] element codes e*64 + a*8 + b sorted by (row, column, code)
+  int32_t* gen_col = nullptr;      // [64 n_el] sorted column nodes (work array of the symbolic step)
+  void* ke = nullptr;              // element Jacobians [n_el][576] (allocated on the first tangent)
 };
 
 namespace fe {
@@ -348,6 +363,22 @@ hipError_t ilu_apply(const fe_problem* p, const void* r, void* z, const int* sto
 hipError_t cgs_init(const fe_problem* p, const void* b, void* x, double rtol, int max_it, hipStream_t s);
 hipError_t cgs_operator(const fe_problem* p, void* x, long j, hipStream_t s);
 int elem_grid_size(int n);  // workgroups of an element-kernel launch (also the partial-sum slots it needs)
+
+// general hex8 meshes (fe_general.hip); TanArgs is defined in fe_device.hpp
+struct TanArgs;
+hipError_t gen_setup(fe_problem* p, const double* coords, const int32_t* conn, hipStream_t s);
+hipError_t gen_check_geometry(const fe_problem* p, double* vol_dev, int* bad, hipStream_t s);
+hipError_t gen_symbolic(fe_problem* p, int32_t* cnt, int32_t* coo_ptr, int32_t* cursor, int32_t* tmp, hipStream_t s,
+                        int64_t* n_pairs, int* max_row);
+int64_t gen_scan_tmp_words(int64_t n);
+hipError_t gen_pairs(fe_problem* p, const int32_t* coo_ptr, hipStream_t s);
+hipError_t gen_csr_pattern(const fe_problem* p, int32_t* row_ptr, int32_t* col_idx, hipStream_t s);
+hipError_t gen_launch_elem(const fe_problem* p, int op, const ElemArgs& a, const int* stop, hipStream_t s);
+hipError_t gen_cg_operator(const fe_problem* p, hipStream_t s);
+hipError_t gen_diag(const fe_problem* p, void* d, int nb, int apply_bc, const TanArgs& ta, hipStream_t s);
+hipError_t gen_tangent(const fe_problem* p, void* vals, int apply_bc, const TanArgs& ta, hipStream_t s);
+hipError_t gen_lift(const fe_problem* p, const double* E, void* u, int zero_free, hipStream_t s);
+hipError_t gen_copy_state(const fe_problem* p, const void* src, void* dst, int64_t n, hipStream_t s);
 // partial-sum slots of a CG operator launch; the update partials (2 * CG_UGRID) follow them
 inline int64_t cg_pa_size(const fe_problem* p) { return std::max<int64_t>(elem_grid_size(p->n), SPMV_MAXGRID); }
 

@@ -48,6 +48,8 @@ class NewtonInfo(ctypes.Structure):
 # (name, restype, argtypes) of every exported entry point
 SIGNATURES = [
     ("fe_problem_create", _i32, [ctypes.POINTER(_vp), _i32, _i32]),
+    ("fe_problem_create_hex8", _i32, [ctypes.POINTER(_vp), _i64, _i64, _vp, _vp, _i32, _vp]),
+    ("fe_commit_state", _i32, [_vp, _vp, _vp, _vp]),
     ("fe_problem_destroy", None, [_vp]),
     ("fe_problem_sizes", _i32, [_vp, ctypes.POINTER(_i64)]),
     ("fe_set_materials", _i32, [_vp, _vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_dbl), _vp, _vp]),
@@ -135,9 +137,11 @@ class PcgResult:
 
 
 class Problem:
-    """Structured n^3 hex8 RVE problem on the current GPU (precision 'f64' or 'f32')."""
+    """Hex8 RVE problem on the current GPU (precision 'f64' or 'f32'): the structured n^3 mesh
+    of the unit cube, or a general mesh given as mesh=(coords (n_nodes, 3), conn (n_el, 8))
+    (numpy or torch; node ids of each element in the local order of include/fe.h)."""
 
-    def __init__(self, n: int, precision: str = "f64", device=None):
+    def __init__(self, n: int | None = None, precision: str = "f64", device=None, mesh=None):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the finite-element library runs on the GPU only")
         self.lib = load_library()
@@ -146,7 +150,17 @@ class Problem:
         self.dtype = torch.float64 if self.prec == F64 else torch.float32
         h = _vp()
         with torch.cuda.device(self.device):
-            _check(self.lib.fe_problem_create(ctypes.byref(h), int(n), self.prec), "fe_problem_create")
+            if mesh is None:
+                _check(self.lib.fe_problem_create(ctypes.byref(h), int(n), self.prec), "fe_problem_create")
+            else:
+                coords = torch.as_tensor(mesh[0], dtype=torch.float64)
+                conn = torch.as_tensor(mesh[1])
+                if coords.ndim != 2 or coords.shape[1] != 3 or conn.ndim != 2 or conn.shape[1] != 8:
+                    raise ValueError("mesh must be (coords (n_nodes, 3), conn (n_el, 8))")
+                c_soa = coords.t().contiguous().to(self.device)              # [3][n_nodes]
+                e_soa = conn.to(torch.int32).t().contiguous().to(self.device)  # [8][n_el]
+                _check(self.lib.fe_problem_create_hex8(ctypes.byref(h), coords.shape[0], conn.shape[0], _ptr(c_soa),
+                                                       _ptr(e_soa), self.prec, _stream()), "fe_problem_create_hex8")
         self.handle = h
         sz = (_i64 * 6)()
         _check(self.lib.fe_problem_sizes(h, sz), "fe_problem_sizes")
@@ -176,6 +190,12 @@ class Problem:
 
     def state(self):
         return torch.zeros(7 * 8 * self.n_el, dtype=self.dtype, device=self.device)
+
+    def commit_state(self, trial, state):
+        """state <- trial (the plastic history of a converged step)."""
+        self._real(trial, 7 * 8 * self.n_el, "trial")
+        self._real(state, 7 * 8 * self.n_el, "state")
+        _check(self.lib.fe_commit_state(self.handle, _ptr(trial), _ptr(state), _stream()), "fe_commit_state")
 
     # -- setup ---------------------------------------------------------------------
     def set_materials(self, phase, models, params, scale=None):
