@@ -22,7 +22,8 @@ Further legs (outside the timed region, each recorded in its own entry): K*u
 rates of both operators, the FP32 ramp, the 96^3 surrogate against the return
 map, the assembled operator at 96^3 and 128^3, the plastic-path adjoint and the
 phase-modulus inverse problem at 64^3, the 128^3 Neo-Hookean leg (FP32 element kernels
-with FP64 reductions against the FP64 run, with its own roofline), and
+with FP64 reductions against the FP64 run, with its own roofline), the general-mesh path at
+64^3 beside the structured kernels, and
 the FP64 CPU oracle on a sample of the same workload.
 """
 from __future__ import annotations
@@ -342,6 +343,80 @@ def csr_scaling_leg(sizes):
     return out
 
 
+def general_leg(n, reps=20):
+    """General-mesh path (fe_problem_create_hex8) at n^3 beside the structured kernels: the fiber RVE
+    (J2 matrix) on the plain grid fed through the general path, and on a distorted, renumbered mesh
+    of the same size, linearised at an affine strain eps_xx = 0.01.  Reports per-kernel times from the
+    library's own events (residual, matrix-free K*u, CSR mat-vec), the whole fe_tangent_csr call
+    (matrix-core element Jacobians plus the sorted gather) from stream events, one CG iteration, and
+    the one-time symbolic set-up."""
+    import torch
+    from paper_2604_22087_amd import fe, inputs
+    out = {}
+    eb = np.diag([0.01, 0.0, 0.0])
+    for name, amp, perm in (("structured", None, False), ("grid_general", 0.0, False), ("distorted_general", 0.25, True)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        coords, conn = inputs.distorted_cube_mesh(n, amplitude=amp or 0.0, seed=7, permute=perm)
+        if amp is None:  # the plain grid numbers nodes and elements as the structured problem does
+            P, _ = setup(n, "f64")
+        else:
+            P = fe.Problem(precision="f64", mesh=(coords, conn))
+            P.set_materials(torch.tensor(inputs.fiber_phase_mesh(coords, conn), device="cuda"), [fe.J2, fe.LINEAR],
+                            [MATRIX, FIBER + (0.0, 0.0)])
+            P.set_dirichlet(torch.tensor(inputs.boundary_dof_mask_mesh(coords), device="cuda"))
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        u = torch.tensor((coords @ eb.T).ravel(), device="cuda")  # the affine field at every node
+        st = P.state()
+        x = torch.randn(P.n_dof, dtype=torch.float64, device="cuda", generator=torch.Generator(device="cuda").manual_seed(0))
+        y = P.vector()
+        rp, ci = P.csr_indices()
+        vals = P.tangent_csr(u, st, apply_bc=True)
+        P.residual(u, st, P.state(), apply_bc=True, store_tangent=True)
+        for _ in range(3):
+            P.apply_matfree(x, y, apply_bc=True)
+            P.tangent_csr(u, st, vals=vals, apply_bc=True)
+        torch.cuda.synchronize()
+        P.profile(True)
+        r = P.vector()
+        for _ in range(reps):
+            P.residual(u, st, None, r=r, apply_bc=True)
+            P.apply_matfree(x, y, apply_bc=True)
+            P.apply_csr_nodal(rp, ci, vals, x, y)
+        pr = P.profile_read()
+        P.profile(False)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            P.tangent_csr(u, st, vals=vals, apply_bc=True)
+        e1.record()
+        torch.cuda.synchronize()
+        t_tan = e0.elapsed_time(e1) / reps * 1e-3
+        b = P.residual(u, st, apply_bc=True, store_tangent=True).neg_()
+        torch.cuda.synchronize()
+        e0.record()
+        _, res = P.pcg(b, op=fe.OP_MATFREE, rtol=1e-30, max_it=200, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        t_cg = e0.elapsed_time(e1) * 1e-3 / max(res.iterations, 1)
+        kc, kms, kby = pr["matfree_apply"]
+        rc, rms, _ = pr["residual"]
+        sc, sms, sby = pr["csr_spmv_nodal"]
+        ku = kms / kc * 1e-3
+        sp = sms / sc * 1e-3
+        out[name] = {"setup_seconds": t_setup, "nnz": P.nnz,
+                     "residual_us": 1e3 * rms / rc, "matfree_ku_us": 1e6 * ku, "matfree_gdofs": P.n_dof / ku / 1e9,
+                     "matfree_frac_hbm": kby / kc / ku / 1e9 / HBM_PEAK_GBS,
+                     "csr_nodal_us": 1e6 * sp, "csr_nodal_frac_hbm": sby / sc / sp / 1e9 / HBM_PEAK_GBS,
+                     "tangent_csr_us": 1e6 * t_tan, "cg_iteration_us": 1e6 * t_cg}
+        del P, u, st, x, y, vals, r, b, rp, ci, coords, conn
+        torch.cuda.empty_cache()
+    out["workload"] = (f"{n}^3 fiber RVE (J2 matrix), linearised at eps_xx = 0.01: structured kernels; the same grid "
+                       f"through the general-mesh path; a distorted, renumbered {n}^3 mesh (amplitude 0.25 h)")
+    return out
+
+
 def cpu_baseline(n, phase, gpu_info, path):
     """The FP64 oracle on a bounded sample of the same workload, on one host core with the BLAS
     pool limited to one thread, extrapolated to one step.  One evaluation is repeated with the
@@ -414,6 +489,7 @@ def main():
     ap.add_argument("--adjoint-path", type=int, default=64, help="n of the plastic-path adjoint leg (0: skip)")
     ap.add_argument("--inverse", type=int, default=64, help="n of the inverse-problem leg (0: skip)")
     ap.add_argument("--csr-sizes", default="96,128", help="mesh sizes of the assembled-operator leg ('' to skip)")
+    ap.add_argument("--general", type=int, default=64, help="n of the general-mesh leg (0: skip)")
     ap.add_argument("--copy-calib", action="store_true", help="run only a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -522,6 +598,9 @@ def main():
     if args.nh:
         print(f"[bench] neo-hookean leg {args.nh}^3", file=sys.stderr, flush=True)
         out["neohooke"] = _leg(neohooke_leg, args.nh)
+    if args.general:
+        print(f"[bench] general-mesh leg {args.general}^3", file=sys.stderr, flush=True)
+        out["general_mesh"] = _leg(general_leg, args.general)
     if not args.no_cpu:
         print("[bench] cpu oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(n, phase, infos[-1], path)

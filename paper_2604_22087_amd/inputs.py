@@ -212,6 +212,19 @@ def sphere_phase_mesh(coords, conn, radius: float = 0.3, center=(0.5, 0.5, 0.5))
     return (np.einsum("ij,ij->i", d, d) < radius * radius).astype(np.uint8)
 
 
+def fiber_phase_mesh(coords, conn, n_fibers: int = 64, radius: float = 0.05, seed: int = 2) -> np.ndarray:
+    """fiber_phase on a general mesh: phase 1 where the element's node-mean centroid (x,y)
+    lies strictly within radius of a fiber center (minimum image)."""
+    centers = rsa_fiber_centers(n_fibers, radius, seed)
+    xy = mesh_centroids(coords, conn)[:, :2]
+    phase = np.zeros(len(xy), dtype=np.uint8)
+    for c in centers:
+        d = xy - c
+        d -= np.round(d)
+        phase |= (np.einsum("ij,ij->i", d, d) < radius * radius).astype(np.uint8)
+    return phase
+
+
 def boundary_dof_mask_mesh(coords, tol: float = 1e-12) -> np.ndarray:
     """uint8 per dof: 1 for all three dofs of every node on a face of the unit cube."""
     c = np.asarray(coords)
