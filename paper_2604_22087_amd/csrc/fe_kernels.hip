@@ -1075,6 +1075,32 @@ constexpr int SPMV_LPR = 16;
 // Node-structured CSR (the pattern of the structured mesh): rows 3a, 3a+1, 3a+2 share one
 // column list, so the column indices and the gathered x of the first row serve all three.
 // LPN lanes per node; y = A x.
+// Partial sums of the three rows b0, b1, b2 (one column list) against x for the columns
+// k = lane, lane + LPN, ...: two column steps per batch, all their index loads, gathers and
+// values issued before the multiply-adds (measured at 64^3 / 128^3: 0.44 -> 0.52-0.58 of 8 TB/s
+// in FP32, 0.57 -> 0.63-0.65 in FP64, against one step at a time).
+template <typename T, int LPN>
+__device__ __forceinline__ void nodal_row_dot(const int32_t* __restrict__ ci, const T* __restrict__ v,
+                                              const T* __restrict__ x, int b0, int b1, int b2, int len, int lane,
+                                              T& a0, T& a1, T& a2) {
+  int k = lane;
+  for (; k + LPN < len; k += 2 * LPN) {
+    const int c0 = ci[b0 + k], c1 = ci[b0 + k + LPN];
+    const T v00 = v[b0 + k], v10 = v[b1 + k], v20 = v[b2 + k];
+    const T v01 = v[b0 + k + LPN], v11 = v[b1 + k + LPN], v21 = v[b2 + k + LPN];
+    const T x0 = x[c0], x1 = x[c1];
+    a0 += v00 * x0 + v01 * x1;
+    a1 += v10 * x0 + v11 * x1;
+    a2 += v20 * x0 + v21 * x1;
+  }
+  if (k < len) {
+    const T xv = x[ci[b0 + k]];
+    a0 += v[b0 + k] * xv;
+    a1 += v[b1 + k] * xv;
+    a2 += v[b2 + k] * xv;
+  }
+}
+
 template <typename T, int LPN>
 __global__ __launch_bounds__(256) void spmv_nodal_kernel(int64_t n_nodes, const int32_t* __restrict__ rp,
                                                          const int32_t* __restrict__ ci, const T* __restrict__ v,
@@ -1087,12 +1113,7 @@ __global__ __launch_bounds__(256) void spmv_nodal_kernel(int64_t n_nodes, const 
   if (nd < n_nodes) {
     const int b0 = rp[3 * nd], b1 = rp[3 * nd + 1], b2 = rp[3 * nd + 2];
     const int len = b1 - b0;
-    for (int k = lane; k < len; k += LPN) {
-      const T xv = x[ci[b0 + k]];
-      a0 += v[b0 + k] * xv;
-      a1 += v[b1 + k] * xv;
-      a2 += v[b2 + k] * xv;
-    }
+    nodal_row_dot<T, LPN>(ci, v, x, b0, b1, b2, len, lane, a0, a1, a2);
   }
 #pragma unroll
   for (int off = LPN / 2; off > 0; off >>= 1) {
@@ -1649,12 +1670,7 @@ __global__ __launch_bounds__(256) void cg_spmv_nodal_kernel(int64_t n_nodes, con
     if (nd < n_nodes) {
       const int b0 = rp[3 * nd], b1 = rp[3 * nd + 1], b2 = rp[3 * nd + 2];
       const int len = b1 - b0;
-      for (int k = lane; k < len; k += LPN) {
-        const T xv = p[ci[b0 + k]];
-        a0 += v[b0 + k] * xv;
-        a1 += v[b1 + k] * xv;
-        a2 += v[b2 + k] * xv;
-      }
+      nodal_row_dot<T, LPN>(ci, v, p, b0, b1, b2, len, lane, a0, a1, a2);
     }
 #pragma unroll
     for (int off = LPN / 2; off > 0; off >>= 1) {

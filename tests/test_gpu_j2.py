@@ -71,6 +71,10 @@ def test_j2_residual_state_tangent(n, prec):
     r_g = P.residual(ut, s_in, s_out, store_tangent=True)
     assert rel_err(_np(r_g), R) <= tol
     ep_g, al_g = state_from_lib(_np(s_out), rve.conn.shape[0])
+    # FP32 history: the plastic increment is dgamma = f_trial / (3G + H) with f_trial = q_trial -
+    # (sigma_y + H alpha_n), a difference of nearly equal numbers at points just past yield, so its
+    # relative rounding error is ~6e-8 x q_trial / f_trial (up to ~1e3 at the barely plastic points
+    # of this field); normwise over all points that gives the 1e-4 bar (FP64: 1e-11)
     assert rel_err(ep_g, trial["eps_p"]) <= (1e-11 if prec == "f64" else 1e-4)
     assert rel_err(al_g, trial["alpha"]) <= (1e-11 if prec == "f64" else 1e-4)
     flips = int(np.sum((al_g > st["alpha"]) != trial["plastic"]))
