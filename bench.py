@@ -93,7 +93,7 @@ def setup(n, prec):
     return P, phase
 
 
-def run_ramp(P, u, state, path):
+def run_ramp(P, u, state, path, predictor=0):
     """Newton tolerances: 1e-8 / 1e-10 in FP64; FP32 residuals carry rounding noise near 1e-7
     relative, so the FP32 run stops at 1e-5 / 1e-6 and its error against FP64 is reported."""
     from paper_2604_22087_amd import fe
@@ -101,7 +101,26 @@ def run_ramp(P, u, state, path):
     state.zero_()
     f64 = P.prec == fe.F64
     return P.newton(path, u=u, state=state, op=fe.OP_MATFREE, assemble_csr=True,
-                    newton_rtol=1e-8 if f64 else 1e-5, pcg_rtol=1e-10 if f64 else 1e-6, max_newton=30)
+                    newton_rtol=1e-8 if f64 else 1e-5, pcg_rtol=1e-10 if f64 else 1e-6, max_newton=30,
+                    predictor=predictor)
+
+
+def predictor_leg(P, path, sig_ref):
+    """The same FP64 ramp with the extrapolating Newton predictor (previous converged increment,
+    scaled to the load increment) against the boundary-only predictor of the timed steps."""
+    import torch
+    from paper_2604_22087_amd import fe
+    u, state = P.vector(), P.state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, sig, info = run_ramp(P, u, state, path, predictor=fe.PREDICT_EXTRAPOLATE)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s_new = np.array([x[0] for x in sig])
+    s_ref = np.array([x[0] for x in sig_ref])
+    return {"seconds": dt, "newton_iterations": info["newton_iterations"],
+            "line_search_halvings": info["line_search_halvings"], "pcg_iterations": info["pcg_iterations"],
+            "per_step": info["steps"], "sigma_bar_xx_max_rel_diff": float(np.max(np.abs(s_new - s_ref) / np.abs(s_ref)))}
 
 
 def operator_rates(P, u, state, reps=50):
@@ -562,9 +581,15 @@ def main():
         "tangent_csr_avg_us": 1e3 * tms / max(tcnt, 1),
         "newton_iterations": infos[-1]["newton_iterations"], "pcg_iterations": infos[-1]["pcg_iterations"],
         "ku_applies": infos[-1]["operator_applies"],
+        "line_search_halvings": infos[-1]["line_search_halvings"],
+        "per_step": {"fields": ["newton_iterations", "line_search_halvings", "cg_iterations"],
+                     "last_timed_step": infos[-1]["steps"],
+                     "newton_iterations_over_timed_steps": [i["newton_iterations"] for i in infos]},
         "sigma_bar_xx_last": sig[-1][0],
     }
     out["operators_f64"] = operator_rates(P, u, state)
+    print("[bench] predictor leg", file=sys.stderr, flush=True)
+    out["extrapolating_predictor"] = _leg(predictor_leg, P, path, sig)
     if not args.no_fp32:
         P32, _ = setup(n, "f32")
         u32, s32 = P32.vector(), P32.state()

@@ -87,7 +87,16 @@ typedef struct {
   int pcg_max_it;        /* inner CG iteration limit */
   int solver;            /* FE_SOLVER_CG (symmetric tangents), FE_SOLVER_BICGSTAB or FE_SOLVER_GMRES */
   int restart;           /* GMRES restart length (1..64; 0 = 30) */
+  int predictor;         /* start of load step k >= 2: FE_PREDICT_BOUNDARY moves only the boundary values
+                            to the new macro strain; FE_PREDICT_EXTRAPOLATE first adds
+                            (|E_k - E_{k-1}| / |E_{k-1} - E_{k-2}|) (u_{k-1} - u_{k-2}) to the free
+                            values (linear extrapolation of the converged path, Frobenius norms of
+                            the macro-strain increments) */
+  int* step_log_host;    /* NULL, or [n_steps][3] host ints: per load step the Newton iterations,
+                            line-search halvings and inner Krylov iterations (filled as steps end) */
 } fe_newton_opts;
+
+enum { FE_PREDICT_BOUNDARY = 0, FE_PREDICT_EXTRAPOLATE = 1 };
 
 typedef struct {
   int newton_iterations; /* summed over load steps */
@@ -300,6 +309,21 @@ int fe_vjp_path(fe_problem* p, const void* u, const void* state_in, const void* 
 int fe_newton(fe_problem* p, const double* load_path_host, int n_steps, const fe_newton_opts* opts,
               void* u, void* state, double* sigma_bar_host, fe_newton_info* info_host,
               void* stream);
+
+/* Deterministic mode (on = 1) of a structured problem: the residual, the matrix-free operator
+ * and the Jacobi diagonal (R(u), K x and diag K of Sec. II-A) sum element contributions in a
+ * fixed order instead of with floating-point atomics -- each element writes its 24 nodal
+ * values to a library buffer (24 n_el reals, allocated here; FE_ERR_OOM if that fails) and
+ * one pass sums, per dof, the (up to 8) elements around its node in element order -- the
+ * volume-averaged stress sums per-workgroup partials in order, and matrix-free CG runs its
+ * unfused form (operator, update and direction launches; the fused launch's atomic slot sums
+ * are not used).  Results are then bit-identical from run to run on one GPU (same inputs,
+ * launch configuration and library build), so Newton and Krylov iteration counts become
+ * reproducible; they equal the default mode's up to rounding order.  Not covered: node-block
+ * Jacobi built from the stored linearisation (use it with the assembled matrix), the learned
+ * surrogate's sample lists (their slot order varies; values do not).  General meshes:
+ * FE_ERR_ARG.  on = 0 returns to the default (faster) mode. */
+int fe_set_deterministic(fe_problem* p, int on);
 
 /* Commit the plastic history of a converged load step (the state update that ends
  * each Newton solve of Sec. II-A / V-A): state = state_trial, both real [7][8][n_el]

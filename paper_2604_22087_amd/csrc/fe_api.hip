@@ -146,6 +146,9 @@ void fe_problem_destroy(fe_problem* p) {
   free_dev(p->bicg_ctrl);
   free_dev(p->w_v);
   free_dev(p->w_v2);
+  free_dev(p->w_uprev);
+  free_dev(p->w_elf);
+  free_dev(p->stress_part);
   free_dev(p->w_state);
   free_dev(p->partials);
   free_dev(p->counter);
@@ -531,6 +534,18 @@ int fe_mean_stress(fe_problem* p, const void* u, const void* state_in, double* s
   return FE_OK;
 }
 
+int fe_set_deterministic(fe_problem* p, int on) {
+  CHKP(p);
+  if (on && p->general) return arg_error("deterministic mode is available on structured problems");
+  if (on) {
+    if (!p->w_elf && alloc(&p->w_elf, real_size(p) * 24 * (size_t)p->n_el)) return FE_ERR_OOM;
+    if (!p->stress_part && alloc((void**)&p->stress_part, sizeof(double) * 6 * (size_t)elem_grid_size(p->n)))
+      return FE_ERR_OOM;
+  }
+  p->deterministic = on ? 1 : 0;
+  return FE_OK;
+}
+
 int fe_commit_state(fe_problem* p, const void* state_trial, void* state, void* stream) {
   CHKP(p);
   if (!state_trial || !state) return arg_error("state_trial and state are required");
@@ -752,7 +767,7 @@ static int pcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci, 
   } else {
     HIPCHK(launch_diag(p, p->w_d, 1, s));
   }
-  const bool fused = op == FE_OP_MATFREE && !p->general;
+  const bool fused = op == FE_OP_MATFREE && !p->general && !p->deterministic;
   if (fused) {
     if (!p->w_cg && alloc(&p->w_cg, 6 * real_size(p) * (size_t)p->n_dof)) return FE_ERR_OOM;
     HIPCHK(cgs_init(p, b, x, rtol, max_it, s));
@@ -1102,12 +1117,16 @@ extern "C" int fe_newton(fe_problem* p, const double* path, int n_steps, const f
     return arg_error("invalid Newton options");
   if (o->solver < FE_SOLVER_CG || o->solver > FE_SOLVER_GMRES) return arg_error("opts.solver is not a solver");
   if (o->restart < 0 || o->restart > GM_MAXM) return arg_error("opts.restart must be in [0, 64]");
+  if (o->predictor != FE_PREDICT_BOUNDARY && o->predictor != FE_PREDICT_EXTRAPOLATE)
+    return arg_error("opts.predictor must be FE_PREDICT_BOUNDARY or FE_PREDICT_EXTRAPOLATE");
   if (p->model_set == MS_J2 && !state) return arg_error("J2 problems need a state array");
   hipStream_t s = S(stream);
   const size_t rs = real_size(p), vec = rs * p->n_dof;
   if (!p->w_v && alloc(&p->w_v, vec)) return FE_ERR_OOM;
   if (!p->w_v2 && alloc(&p->w_v2, vec)) return FE_ERR_OOM;
   if (p->model_set == MS_J2 && !p->w_state && alloc(&p->w_state, rs * 7 * 8 * p->n_el)) return FE_ERR_OOM;
+  const bool extrapolate = o->predictor == FE_PREDICT_EXTRAPOLATE && n_steps > 2;
+  if (extrapolate && !p->w_uprev && alloc(&p->w_uprev, vec)) return FE_ERR_OOM;
   const bool use_csr = o->op == FE_OP_CSR || o->assemble_csr;
   if (use_csr) {
     if (int st = check_csr_size(p)) return st;
@@ -1142,7 +1161,28 @@ extern "C" int fe_newton(fe_problem* p, const double* path, int n_steps, const f
     return FE_OK;
   };
   const int max_halvings = 5;
+  auto frob_step = [&](int k) {  // |E_k - E_{k-1}| (E_{-1} = 0)
+    double a = 0;
+    for (int i = 0; i < 9; ++i) {
+      const double d = path[9 * k + i] - (k > 0 ? path[9 * (k - 1) + i] : 0.0);
+      a += d * d;
+    }
+    return std::sqrt(a);
+  };
   for (int step = 0; step < n_steps; ++step) {
+    const fe_newton_info at_start = inf;
+    if (extrapolate) {
+      // w_uprev holds u_{k-2} from step 2 on; u += ratio (u - w_uprev), then w_uprev <- the old u
+      if (step >= 2) {
+        const double d0 = frob_step(step - 1);
+        const double ratio = d0 > 0 ? frob_step(step) / d0 : 0.0;
+        HIPCHK(launch_axpby(p, p->n_dof, 1.0, u, 0.0, w, s));                // w = u_{k-1}
+        HIPCHK(launch_axpby(p, p->n_dof, -ratio, p->w_uprev, 1.0 + ratio, u, s));  // u = u + ratio (u - u_{k-2})
+        HIPCHK(launch_axpby(p, p->n_dof, 1.0, w, 0.0, p->w_uprev, s));       // u_{k-2} <- u_{k-1}
+      } else {
+        HIPCHK(launch_axpby(p, p->n_dof, 1.0, u, 0.0, p->w_uprev, s));
+      }
+    }
     HIPCHK(launch_lift(p, path + 9 * step, u, 0, s));
     double r0 = -1.0, rn = 0.0;
     bool converged = false;
@@ -1209,6 +1249,11 @@ extern "C" int fe_newton(fe_problem* p, const double* path, int n_steps, const f
     }
     if (trial) HIPCHK(gen_copy_state(p, trial, state, 7 * 8 * p->n_el, s));
     inf.steps_done += 1;
+    if (o->step_log_host) {
+      o->step_log_host[3 * step] = inf.newton_iterations - at_start.newton_iterations;
+      o->step_log_host[3 * step + 1] = inf.line_search_halvings - at_start.line_search_halvings;
+      o->step_log_host[3 * step + 2] = inf.pcg_iterations - at_start.pcg_iterations;
+    }
   }
   HIPCHK(hipStreamSynchronize(s));
   if (info) *info = inf;

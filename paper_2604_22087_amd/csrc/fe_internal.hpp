@@ -166,6 +166,11 @@ struct ElemArgs {
   const double* cg_acc_in;// [3][CGS_SLOTS] sums of launch j-1: (u, A u), (r, u), ||r||^2
   double* cg_acc_out;     // [3][CGS_SLOTS] sums of launch j (atomics; zeroed by launch j-1)
   double* cg_acc_zero;    // [3][CGS_SLOTS] slots of launch j+1 (zeroed by workgroup 0)
+  // deterministic mode (fe_set_deterministic; RESID and APPLY only): element nodal forces go to
+  // elf [24][n_el] (corner-major, corner = i + 2 j + 4 k, then component) instead of being summed
+  // with atomics; the stress integral goes to per-workgroup partials stress_part [grid][6]
+  void* elf;
+  double* stress_part;
 };
 
 template <typename T> struct Buf { T* p = nullptr; };
@@ -209,6 +214,10 @@ struct fe_problem {
   fe::BicgCtrl* bicg_ctrl = nullptr;
   void* w_v = nullptr;        // scratch vector (Newton)
   void* w_v2 = nullptr;       // scratch vector (Newton)
+  void* w_uprev = nullptr;    // Newton with the extrapolating predictor: the converged u two steps back
+  int deterministic = 0;      // fe_set_deterministic: fixed summation orders, no floating-point atomics
+  void* w_elf = nullptr;      // deterministic mode: element nodal forces [24][n_el]
+  double* stress_part = nullptr;  // deterministic mode: per-workgroup stress partials [elem grid][6]
   void* w_state = nullptr;    // J2 trial state (Newton)
   double* partials = nullptr; // block partial sums (double)
   unsigned int* counter = nullptr;
@@ -379,6 +388,13 @@ hipError_t gen_diag(const fe_problem* p, void* d, int nb, int apply_bc, const Ta
 hipError_t gen_tangent(const fe_problem* p, void* vals, int apply_bc, const TanArgs& ta, hipStream_t s);
 hipError_t gen_lift(const fe_problem* p, const double* E, void* u, int zero_free, hipStream_t s);
 hipError_t gen_copy_state(const fe_problem* p, const void* src, void* dst, int64_t n, hipStream_t s);
+// deterministic mode, structured problems: sum per-element nodal values (elf [24][n_el]) into y
+// in fixed element order; mode 0 residual (constrained dofs 0 when apply_bc), 1 operator
+// (constrained dofs y = x when apply_bc), 2 diagonal (constrained dofs 1 when apply_bc); with
+// pa, per-workgroup partials of x.y (GEN_CG_GRID workgroups) for CG
+hipError_t det_gather(const fe_problem* p, const void* elf, int mode, int apply_bc, const void* x, void* y,
+                      const int* stop, double* pa, hipStream_t s);
+hipError_t det_stress_reduce(const fe_problem* p, hipStream_t s);
 // partial-sum slots of a CG operator launch; the update partials (2 * CG_UGRID) follow them
 inline int64_t cg_pa_size(const fe_problem* p) { return std::max<int64_t>(elem_grid_size(p->n), SPMV_MAXGRID); }
 

@@ -380,7 +380,11 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
   const int nb = ntx * nty * ntz;
   const int per = (nb + 7) >> 3;
   const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  if (tile >= nb) return;  // padding block of the XCD-aware numbering
+  if (tile >= nb) {  // padding block of the XCD-aware numbering
+    if constexpr (OP == OP_RESID)  // (deterministic mode sums every workgroup's stress slot)
+      if (a.stress_part && a.stress_sum && threadIdx.x < 6) a.stress_part[(int64_t)blockIdx.x * 6 + threadIdx.x] = 0.0;
+    return;
+  }
   const int a0 = (tile % ntx) * TX, b0 = ((tile / ntx) % nty) * TY, c0 = (tile / (ntx * nty)) * TZ;
   const int tid = threadIdx.x;
   const T* X = static_cast<const T*>(a.x);
@@ -660,6 +664,33 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
     }
   }
 
+  // deterministic mode: the element's nodal forces to the per-element buffer (summed later in
+  // fixed order by det_gather), the stress integral to this workgroup's partial slot
+  if constexpr (OP == OP_RESID || OP == OP_APPLY) {
+    if (a.elf) {
+      if (valid) {
+        T* F = static_cast<T*>(a.elf);
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) F[(int64_t)(3 * (i + 2 * j + 4 * k) + c) * ne + e] = Fo[k][j][i][c];
+      }
+      if (OP == OP_RESID && a.stress_sum) {
+        __syncthreads();
+        if (tid < 6) {
+          double v = 0;
+          for (int w = 0; w < EBLOCK / 64; ++w) v += s_red[tid][w];
+          a.stress_part[(int64_t)blockIdx.x * 6 + tid] = v;
+        }
+      }
+      return;
+    }
+  }
+
   if (OP == OP_VJP) {
     if (valid) {
       // the element's nodal forces sum to zero, so lambda may be taken relative to its
@@ -791,6 +822,17 @@ static hipError_t launch_elem_t(const fe_problem* p, const ElemArgs& a, const in
 
 template <typename T>
 static hipError_t launch_elem_op(const fe_problem* p, int op, const ElemArgs& a, const int* stop, hipStream_t s) {
+  if (p->deterministic && (op == OP_RESID || op == OP_APPLY)) {
+    // element forces to the buffer, then the fixed-order node gather (no atomics)
+    ElemArgs d = a;
+    d.elf = p->w_elf;
+    d.stress_part = p->stress_part;
+    hipError_t e = op == OP_RESID ? launch_elem_t<T, OP_RESID>(p, d, stop, s) : launch_elem_t<T, OP_APPLY>(p, d, stop, s);
+    if (e != hipSuccess) return e;
+    if (op == OP_RESID && a.stress_sum && (e = det_stress_reduce(p, s)) != hipSuccess) return e;
+    if (!a.y) return hipSuccess;
+    return det_gather(p, p->w_elf, op == OP_RESID ? 0 : 1, a.apply_bc, a.x, a.y, stop, nullptr, s);
+  }
   if (op == OP_RESID) return launch_elem_t<T, OP_RESID>(p, a, stop, s);
   if (op == OP_APPLY) return launch_elem_t<T, OP_APPLY>(p, a, stop, s);
   return launch_elem_t<T, OP_VJP>(p, a, stop, s);
@@ -834,7 +876,7 @@ static TanArgs tan_args(const fe_problem* p) {
 
 // Diagonal of K: one lane per element, 24 entries added atomically (d zeroed before).
 template <typename T, int MS>
-__global__ __launch_bounds__(256) void diag_kernel(TanArgs a, T* d) {
+__global__ __launch_bounds__(256) void diag_kernel(TanArgs a, T* d, T* elf) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= a.n_el) return;
   const int n = a.n;
@@ -866,8 +908,12 @@ __global__ __launch_bounds__(256) void diag_kernel(TanArgs a, T* d) {
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-          atomic_add(d + 3 * ((ea + i) + np1 * ((eb + j) + np1 * (ec + k))) + c, acc[k][j][i][c]);
+        for (int c = 0; c < 3; ++c) {
+          if (elf)  // deterministic mode: summed later in fixed element order
+            elf[(int64_t)(3 * (i + 2 * j + 4 * k) + c) * a.n_el + e] = acc[k][j][i][c];
+          else
+            atomic_add(d + 3 * ((ea + i) + np1 * ((eb + j) + np1 * (ec + k))) + c, acc[k][j][i][c]);
+        }
 }
 
 template <typename T> __global__ void mask_set_kernel(T* x, const uint8_t* mask, int64_t n, T v) {
@@ -893,14 +939,16 @@ hipError_t launch_fill(const fe_problem* p, void* x, int64_t n, double v, hipStr
 }
 
 template <typename T> static hipError_t launch_diag_t(const fe_problem* p, T* d, int apply_bc, hipStream_t s) {
-  hipLaunchKernelGGL(fill_kernel<T>, dim3(vgrid(p->n_dof)), dim3(VBLOCK), 0, s, d, p->n_dof, T(0));
+  T* elf = p->deterministic ? static_cast<T*>(p->w_elf) : nullptr;
+  if (!elf) hipLaunchKernelGGL(fill_kernel<T>, dim3(vgrid(p->n_dof)), dim3(VBLOCK), 0, s, d, p->n_dof, T(0));
   const TanArgs a = tan_args(p);
   const dim3 grid((unsigned)((p->n_el + 255) / 256));
   switch (p->model_set) {
-    case MS_J2: hipLaunchKernelGGL((diag_kernel<T, MS_J2>), grid, dim3(256), 0, s, a, d); break;
-    case MS_NH: hipLaunchKernelGGL((diag_kernel<T, MS_NH>), grid, dim3(256), 0, s, a, d); break;
-    default: hipLaunchKernelGGL((diag_kernel<T, MS_LINEAR>), grid, dim3(256), 0, s, a, d);
+    case MS_J2: hipLaunchKernelGGL((diag_kernel<T, MS_J2>), grid, dim3(256), 0, s, a, d, elf); break;
+    case MS_NH: hipLaunchKernelGGL((diag_kernel<T, MS_NH>), grid, dim3(256), 0, s, a, d, elf); break;
+    default: hipLaunchKernelGGL((diag_kernel<T, MS_LINEAR>), grid, dim3(256), 0, s, a, d, elf);
   }
+  if (elf) return det_gather(p, elf, 2, apply_bc, nullptr, d, nullptr, nullptr, s);
   if (apply_bc && p->mask)
     hipLaunchKernelGGL(mask_set_kernel<T>, dim3(vgrid(p->n_dof)), dim3(VBLOCK), 0, s, d, p->mask, p->n_dof, T(1));
   return hipGetLastError();
@@ -1695,7 +1743,7 @@ static int cg_spmv_grid(const fe_problem* p) {
 }
 
 static int cg_operator_grid(const fe_problem* p, int op) {
-  if (op != FE_OP_CSR && p->general) return GEN_CG_GRID;
+  if (op != FE_OP_CSR && (p->general || p->deterministic)) return GEN_CG_GRID;
   return op == FE_OP_CSR ? cg_spmv_grid(p) : elem_grid(p->n);
 }
 
@@ -1715,6 +1763,28 @@ static hipError_t cg_operator_t(const fe_problem* p, int op, const int32_t* rp, 
     return hipGetLastError();
   }
   if (p->general) return gen_cg_operator(p, s);
+  if (p->deterministic) {  // q = A p element by element, fixed-order gather with the p.q partials
+    ElemArgs a{};
+    a.n = p->n;
+    a.h = p->h;
+    a.n_el = p->n_el;
+    a.phase = p->phase;
+    a.scale = p->scale;
+    a.mask = p->mask;
+    a.tangent = p->tangent;
+    a.flags = p->flags;
+    a.mat = p->mat;
+    a.sur_map = p->sur_map;
+    a.sur_D = p->sur_D;
+    a.x = p->w_p;
+    a.xlin = p->u_lin;
+    a.y = p->w_q;
+    a.apply_bc = 1;
+    a.elf = p->w_elf;
+    const hipError_t e = launch_elem_t<T, OP_APPLY>(p, a, stop, s);
+    if (e != hipSuccess) return e;
+    return det_gather(p, p->w_elf, 1, 1, p->w_p, p->w_q, stop, p->partials, s);
+  }
   return hipErrorInvalidValue;  // the structured matrix-free operator runs through cgs_operator
 }
 
@@ -1818,7 +1888,7 @@ hipError_t cg_operator(const fe_problem* p, int op, const int32_t* rp, const int
 
 // CSR iterations form the direction in a kernel of their own before the mat-vec.
 template <typename T> static hipError_t cg_pre_t(const fe_problem* p, int op, long k, hipStream_t s) {
-  if (op != FE_OP_CSR && !p->general) return hipSuccess;
+  if (op != FE_OP_CSR && !p->general && !p->deterministic) return hipSuccess;
   hipLaunchKernelGGL(cg_direction_kernel<T>, dim3(CG_UGRID), dim3(VBLOCK), 0, s, p->n_dof, (const T*)p->w_r,
                      (const T*)pc_buffer(p), p->precond, (T*)p->w_p, p->ctrl,
                      (const double*)(p->partials + cg_pa_size(p)), k);
@@ -2296,4 +2366,73 @@ hipError_t launch_lin_stats(const fe_problem* p, unsigned long long* out, hipStr
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// deterministic mode: fixed-order sums of per-element nodal values
+
+// One thread per dof: the (up to 8) elements around its node in the order (c, b, a) ascending,
+// each element's value of this node's corner.
+template <typename T>
+__global__ __launch_bounds__(VBLOCK) void det_gather_kernel(int n, int64_t n_el, const T* __restrict__ elf, const uint8_t* mask,
+                                                            int mode, int apply_bc, const T* __restrict__ x, T* __restrict__ y,
+                                                            const int* stop, double* pa) {
+  __shared__ double sh[VBLOCK / 64];
+  if (stop && *stop) return;
+  const int64_t np1 = n + 1, n_dof = 3 * np1 * np1 * np1;
+  double v = 0;
+  for (int64_t d = (int64_t)blockIdx.x * VBLOCK + threadIdx.x; d < n_dof; d += (int64_t)gridDim.x * VBLOCK) {
+    const int64_t P = d / 3;
+    const int c = (int)(d - 3 * P);
+    const int gi = (int)(P % np1), gj = (int)((P / np1) % np1), gk = (int)(P / (np1 * np1));
+    T sum = 0;
+#pragma unroll
+    for (int dk = 1; dk >= 0; --dk)
+#pragma unroll
+      for (int dj = 1; dj >= 0; --dj)
+#pragma unroll
+        for (int di = 1; di >= 0; --di) {
+          const int ea = gi - di, eb = gj - dj, ec = gk - dk;  // element whose corner (di, dj, dk) is this node
+          if (ea < 0 || eb < 0 || ec < 0 || ea >= n || eb >= n || ec >= n) continue;
+          const int64_t e = ea + (int64_t)n * (eb + (int64_t)n * ec);
+          sum += elf[(int64_t)(3 * (di + 2 * dj + 4 * dk) + c) * n_el + e];
+        }
+    if (apply_bc && mask && mask[d]) sum = mode == 0 ? T(0) : (mode == 1 ? x[d] : T(1));
+    y[d] = sum;
+    if (pa) v += (double)x[d] * (double)sum;
+  }
+  if (pa) {
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) pa[blockIdx.x] = v;
+  }
+}
+
+template <typename T>
+static hipError_t det_gather_t(const fe_problem* p, const T* elf, int mode, int apply_bc, const T* x, T* y, const int* stop,
+                               double* pa, hipStream_t s) {
+  const unsigned grid = pa ? (unsigned)GEN_CG_GRID : (unsigned)vgrid(p->n_dof);
+  hipLaunchKernelGGL(det_gather_kernel<T>, dim3(grid), dim3(VBLOCK), 0, s, p->n, p->n_el, elf, p->mask, mode, apply_bc, x,
+                     y, stop, pa);
+  return hipGetLastError();
+}
+
+hipError_t det_gather(const fe_problem* p, const void* elf, int mode, int apply_bc, const void* x, void* y,
+                      const int* stop, double* pa, hipStream_t s) {
+  return p->prec == FE_F64 ? det_gather_t(p, (const double*)elf, mode, apply_bc, (const double*)x, (double*)y, stop, pa, s)
+                           : det_gather_t(p, (const float*)elf, mode, apply_bc, (const float*)x, (float*)y, stop, pa, s);
+}
+
+// stress_sum[k] = sum of the workgroup partials in workgroup order (one thread per component)
+__global__ void det_stress_kernel(const double* part, int nb, double* out) {
+  const int k = threadIdx.x;
+  if (k >= 6) return;
+  double v = 0;
+  for (int b = 0; b < nb; ++b) v += part[(int64_t)b * 6 + k];
+  out[k] = v;
+}
+
+hipError_t det_stress_reduce(const fe_problem* p, hipStream_t s) {
+  hipLaunchKernelGGL(det_stress_kernel, dim3(1), dim3(64), 0, s, p->stress_part, elem_grid(p->n), p->stress_sum);
+  return hipGetLastError();
+}
+
 }  // namespace fe
+

@@ -37,7 +37,11 @@ class PcgInfo(ctypes.Structure):
 
 class NewtonOpts(ctypes.Structure):
     _fields_ = [("op", _i32), ("assemble_csr", _i32), ("max_newton", _i32), ("newton_rtol", _dbl), ("pcg_rtol", _dbl),
-                ("pcg_max_it", _i32), ("solver", _i32), ("restart", _i32)]
+                ("pcg_max_it", _i32), ("solver", _i32), ("restart", _i32), ("predictor", _i32),
+                ("step_log_host", ctypes.POINTER(_i32))]
+
+
+PREDICT_BOUNDARY, PREDICT_EXTRAPOLATE = 0, 1
 
 
 class NewtonInfo(ctypes.Structure):
@@ -50,6 +54,7 @@ SIGNATURES = [
     ("fe_problem_create", _i32, [ctypes.POINTER(_vp), _i32, _i32]),
     ("fe_problem_create_hex8", _i32, [ctypes.POINTER(_vp), _i64, _i64, _vp, _vp, _i32, _vp]),
     ("fe_commit_state", _i32, [_vp, _vp, _vp, _vp]),
+    ("fe_set_deterministic", _i32, [_vp, _i32]),
     ("fe_problem_destroy", None, [_vp]),
     ("fe_problem_sizes", _i32, [_vp, ctypes.POINTER(_i64)]),
     ("fe_set_materials", _i32, [_vp, _vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_dbl), _vp, _vp]),
@@ -190,6 +195,10 @@ class Problem:
 
     def state(self):
         return torch.zeros(7 * 8 * self.n_el, dtype=self.dtype, device=self.device)
+
+    def set_deterministic(self, on=True):
+        """Fixed summation orders (no floating-point atomics) in residual, K*x and diagonal."""
+        _check(self.lib.fe_set_deterministic(self.handle, int(bool(on))), "fe_set_deterministic")
 
     def commit_state(self, trial, state):
         """state <- trial (the plastic history of a converged step)."""
@@ -332,15 +341,19 @@ class Problem:
         return mu_out
 
     def newton(self, load_path, u=None, state=None, op=OP_MATFREE, max_newton=20, newton_rtol=1e-8,
-               pcg_rtol=1e-10, pcg_max_it=100000, assemble_csr=False, check=True, solver=SOLVER_CG, restart=0):
-        """Load stepping; load_path: sequence of 3x3 macro strains. Returns (u, state, sigma_bar, info)."""
+               pcg_rtol=1e-10, pcg_max_it=100000, assemble_csr=False, check=True, solver=SOLVER_CG, restart=0,
+               predictor=PREDICT_BOUNDARY):
+        """Load stepping; load_path: sequence of 3x3 macro strains. Returns (u, state, sigma_bar, info);
+        info["steps"] lists (Newton iterations, line-search halvings, Krylov iterations) per load step."""
         path = torch.as_tensor(np.asarray(load_path, dtype=np.float64)).reshape(-1, 9)
         k = path.shape[0]
         pa = (_dbl * (9 * k))(*path.reshape(-1).tolist())
         u = self.vector() if u is None else self._real(u, self.n_dof, "u")
         self._real(state, 56 * self.n_el, "state")
+        log = (_i32 * (3 * max(k, 1)))()
         opts = NewtonOpts(int(op), int(bool(assemble_csr)), int(max_newton), float(newton_rtol), float(pcg_rtol),
-                          int(pcg_max_it), int(solver), int(restart))
+                          int(pcg_max_it), int(solver), int(restart), int(predictor),
+                          ctypes.cast(log, ctypes.POINTER(_i32)))
         sig = (_dbl * (6 * max(k, 1)))()
         info = NewtonInfo()
         st = self.lib.fe_newton(self.handle, pa, k, ctypes.byref(opts), _ptr(u), _ptr(state), sig,
@@ -348,7 +361,9 @@ class Problem:
         if check:
             _check(st, "fe_newton")
         sb = [list(sig[6 * i:6 * i + 6]) for i in range(k)]
-        return u, state, sb, {f: getattr(info, f) for f, _ in NewtonInfo._fields_}
+        out = {f: getattr(info, f) for f, _ in NewtonInfo._fields_}
+        out["steps"] = [tuple(log[3 * i:3 * i + 3]) for i in range(info.steps_done)]
+        return u, state, sb, out
 
     def mean_stress(self, u, state_in=None):
         self._real(u, self.n_dof, "u")

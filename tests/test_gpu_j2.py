@@ -116,3 +116,34 @@ def test_j2_newton_ramp(op):
         assert rel_err(sig[k], h["sigma_bar"]) <= 1e-9
     # iteration counts are reported, not pinned: rounding may move one iterate across the tolerance
     assert abs(info["newton_iterations"] - sum(len(h["residuals"]) - 1 for h in hist)) <= len(path)
+
+
+def test_j2_newton_extrapolating_predictor():
+    """The extrapolating predictor (previous converged increment scaled to the load increment) reaches
+    the oracle's converged ramp like the boundary-only one; the per-step log adds up to the totals."""
+    import torch
+    from paper_2604_22087_amd import fe
+    n = 6
+    print("[j2 newton predictor]", flush=True)
+    phase = _fiber_phase(n)
+    rve = RVE(n, phase, oracle_phases(PHASES_J2_FIBER))
+    path = [np.diag([0.004 * k, 0.0, 0.0]) for k in range(1, 7)]
+    u_ref, st_ref, hist = rve.newton(path, newton_rtol=1e-11, pcg_rtol=1e-13)
+    P = _problem(n, "f64", phase)
+    P.set_dirichlet(torch.tensor(inputs.boundary_dof_mask(n), device="cuda"))
+    runs = {}
+    for pred in (fe.PREDICT_BOUNDARY, fe.PREDICT_EXTRAPOLATE):
+        u, state, sig, info = P.newton(path, state=P.state(), op=fe.OP_MATFREE, newton_rtol=1e-11, pcg_rtol=1e-13,
+                                       predictor=pred)
+        assert info["steps_done"] == len(path)
+        assert rel_err(_np(u), u_ref) <= 1e-8
+        for k, h in enumerate(hist):
+            assert rel_err(sig[k], h["sigma_bar"]) <= 1e-9
+        steps = info["steps"]
+        assert len(steps) == len(path)
+        assert sum(s[0] for s in steps) == info["newton_iterations"]
+        assert sum(s[1] for s in steps) == info["line_search_halvings"]
+        assert sum(s[2] for s in steps) == info["pcg_iterations"]
+        runs[pred] = info
+    print(f"  Newton iterations: boundary {runs[0]['newton_iterations']}, extrapolated {runs[1]['newton_iterations']}",
+          flush=True)
