@@ -73,7 +73,7 @@ def measured_traffic():
     rec = json.load(open(path))
     src = os.path.join(ROOT, "paper_2604_22087_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("fe_kernels.hip", "fe_internal.hpp"):
+    for f in ("fe_kernels.hip", "fe_internal.hpp", "fe_device.hpp"):
         h.update(open(os.path.join(src, f), "rb").read())
     return rec if h.hexdigest() == rec["source_sha256"] else None
 

@@ -21,6 +21,8 @@
 //   w detJ is one batched contraction on the FP64 / FP32 matrix cores (v_mfma_*_16x16x4),
 //   written to a per-element buffer; a gather then sums every pair's run in sorted order
 //   into the CSR values (deterministic: the same bits on every run).
+#include <type_traits>
+
 #include "fe_internal.hpp"
 #include "fe_device.hpp"
 
@@ -428,39 +430,56 @@ template <typename T> struct Acc4;
 template <> struct Acc4<double> { typedef v4d type; };
 template <> struct Acc4<float> { typedef v4f_t type; };
 
+// Calls f(std::integral_constant<int, i>) for i = 0 .. N-1 (compile-time loop index).
+template <int I, int N, typename F> __device__ __forceinline__ void static_for_impl(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for_impl<I + 1, N>(f);
+  }
+}
+template <int N, typename F> __device__ __forceinline__ void static_for(F&& f) { static_for_impl<0, N>(f); }
+
 // Row of result entry r of lane l (16 x 16 x 4 MFMA).
 template <typename T> __device__ __forceinline__ int mfma_row(int l, int r);
 template <> __device__ __forceinline__ int mfma_row<double>(int l, int r) { return (l >> 4) + 4 * r; }
 template <> __device__ __forceinline__ int mfma_row<float>(int l, int r) { return 4 * (l >> 4) + r; }
 
 // Entry (m, (b, k)) of the stacked gradient operator at one point: Voigt rows
-// [xx yy zz yz xz xy] (DIM 6) or gradient rows (i, J) = 3 i + J (DIM 9).
-template <typename T, int DIM> __device__ __forceinline__ T g_entry(int m, int k, const T* gb) {
-  if (DIM == 9) return (m / 3 == k) ? gb[m % 3] : T(0);
-  switch (m) {
-    case 0: return k == 0 ? gb[0] : T(0);
-    case 1: return k == 1 ? gb[1] : T(0);
-    case 2: return k == 2 ? gb[2] : T(0);
-    case 3: return k == 1 ? gb[2] : (k == 2 ? gb[1] : T(0));
-    case 4: return k == 0 ? gb[2] : (k == 2 ? gb[0] : T(0));
-    default: return k == 0 ? gb[1] : (k == 1 ? gb[0] : T(0));
-  }
+// [xx yy zz yz xz xy] (DIM 6) or gradient rows (i, J) = 3 i + J (DIM 9).  m is a compile-time
+// row of the unrolled contraction loop and k the lane's component, so this is a pair of selects.
+template <typename T, int DIM, int M> __device__ __forceinline__ T g_entry(int k, const T* gb) {
+  if (DIM == 9) return k == M / 3 ? gb[M % 3] : T(0);
+  if (M < 3) return k == M ? gb[M] : T(0);
+  constexpr int ka = M == 3 ? 1 : 0, da = M == 3 ? 2 : (M == 4 ? 2 : 1);   // shear rows: two components
+  constexpr int kb = M == 5 ? 1 : 2, db = M == 3 ? 1 : 0;
+  return k == ka ? gb[da] : (k == kb ? gb[db] : T(0));
 }
 
-// (D G)[m][(b, k)] at one point: the rows n of G's column (b, k) that are non-zero.
-template <typename T, int DIM> __device__ __forceinline__ T dg_entry(const T* D, int m, int k, const T* gb) {
-  const T* Dm = D + m * DIM;
+// Rows of B's column (b, k) that are non-zero (Voigt): row k (d/dx_k) and two shear rows n1, n2
+// with the derivative directions g1, g2 -- per lane constants.
+struct VoigtCol {
+  int n1, g1, n2, g2;
+};
+__device__ __forceinline__ VoigtCol voigt_col(int k) {
+  VoigtCol c;
+  c.n1 = k == 0 ? 4 : 3;
+  c.g1 = k == 2 ? 1 : 2;
+  c.n2 = k == 2 ? 4 : 5;
+  c.g2 = k == 0 ? 1 : 0;
+  return c;
+}
+
+// (D G)[m][(b, k)] at one point.
+template <typename T, int DIM, int M>
+__device__ __forceinline__ T dg_entry(const T* D, int k, const VoigtCol& vc, const T* gb) {
+  const T* Dm = D + M * DIM;
   if (DIM == 9) return Dm[3 * k] * gb[0] + Dm[3 * k + 1] * gb[1] + Dm[3 * k + 2] * gb[2];
-  // column (b, k) of B: rows k (d/dx_k), and the two shear rows that contain component k
-  if (k == 0) return Dm[0] * gb[0] + Dm[4] * gb[2] + Dm[5] * gb[1];
-  if (k == 1) return Dm[1] * gb[1] + Dm[3] * gb[2] + Dm[5] * gb[0];
-  return Dm[2] * gb[2] + Dm[3] * gb[1] + Dm[4] * gb[0];
+  return Dm[k] * gb[k] + Dm[vc.n1] * gb[vc.g1] + Dm[vc.n2] * gb[vc.g2];
 }
 
 template <typename T, int MS>
 __global__ __launch_bounds__(64) void gen_tangent_kernel(GenArgs g, TanArgs ta, T* ke) {
   constexpr int DIM = MS == MS_NH ? 9 : 6;
-  constexpr int KS = 8 * DIM / 4;  // k-steps of 4
   typedef typename Acc4<T>::type acc_t;
   __shared__ T s_xe[8][3];
   __shared__ T s_g[8][8][3];          // [point][node][direction]
@@ -528,19 +547,25 @@ __global__ __launch_bounds__(64) void gen_tangent_kernel(GenArgs g, TanArgs ta, 
     const int ra = r16 / 3, ri = r16 % 3;                 // tile 0 row / column (node, component)
     const int rb = (16 + r16) / 3, rk = (16 + r16) % 3;   // tile 1 (valid for r16 < 8)
     const bool t1 = r16 < 8;
-#pragma unroll 2
-    for (int s = 0; s < KS; ++s) {
-      const int kk = 4 * s + (l >> 4);
-      const int qp = kk / DIM, m = kk % DIM;
+    const VoigtCol va = voigt_col(ri), vb = voigt_col(rk);
+    // contraction index ordered row-major over (m, point): k-step s covers row m = s / 2 of the
+    // points 4 (s % 2) + l / 16, so m is the same on every lane of a step (compile time)
+    auto step = [&](auto mc, int half) {
+      constexpr int M = decltype(mc)::value;
+      const int qp = 4 * half + (l >> 4);
       const T* Dq = s_D[qp];
-      const T a0 = g_entry<T, DIM>(m, ri, s_g[qp][ra]);
-      const T a1 = t1 ? g_entry<T, DIM>(m, rk, s_g[qp][rb]) : T(0);
-      const T b0 = dg_entry<T, DIM>(Dq, m, ri, s_g[qp][ra]);
-      const T b1 = t1 ? dg_entry<T, DIM>(Dq, m, rk, s_g[qp][rb]) : T(0);
+      const T a0 = g_entry<T, DIM, M>(ri, s_g[qp][ra]);
+      const T a1 = t1 ? g_entry<T, DIM, M>(rk, s_g[qp][rb]) : T(0);
+      const T b0 = dg_entry<T, DIM, M>(Dq, ri, va, s_g[qp][ra]);
+      const T b1 = t1 ? dg_entry<T, DIM, M>(Dq, rk, vb, s_g[qp][rb]) : T(0);
       c00 = mfma16(a0, b0, c00);
       c01 = mfma16(a0, b1, c01);
       c11 = mfma16(a1, b1, c11);
-    }
+    };
+    static_for<DIM>([&](auto mc) {
+      step(mc, 0);
+      step(mc, 1);
+    });
     T* K = ke + e * 576;
     const int col = l & 15;
 #pragma unroll

@@ -6,6 +6,12 @@
       launches past convergence that return at once; they are dropped that way)
   python -m paper_2604_22087_amd.rocprof_summary pmc DIR [--kernel SUBSTR]
       per-kernel mean / median / max of each counter from *counter_collection.csv
+  python -m paper_2604_22087_amd.rocprof_summary traffic --fetch DIR --write DIR --cal-fetch DIR
+      --cal-write DIR --bench-json FILE --kernel SUBSTR --workload TEXT
+      HBM bytes per launch of one kernel from a FETCH_SIZE and a WRITE_SIZE run (KiB per dispatch),
+      each scaled by what the same counter reads for a device copy of exactly 1 GiB each way
+      (bench.py --copy-calib runs), next to the algorithmic bytes per launch of the benchmark line
+      in FILE, with the SHA-256 of the kernel sources the counters belong to (JSON)
 """
 from __future__ import annotations
 
@@ -50,15 +56,47 @@ def pmc(root, kernel=""):
     return "\n".join(lines)
 
 
+def _mean_counter(root, counter, kernel):
+    v = [float(r["Counter_Value"] or 0) for r in _rows(root, "counter_collection.csv")
+         if r["Counter_Name"].startswith(counter) and kernel in r["Kernel_Name"]]
+    return statistics.fmean(v), len(v)
+
+
+def traffic(fetch, write, cal_fetch, cal_write, bench_json, kernel, workload):
+    import hashlib
+    import json
+    f_kib, nf = _mean_counter(fetch, "FETCH_SIZE", kernel)
+    w_kib, nw = _mean_counter(write, "WRITE_SIZE", kernel)
+    cf, _ = _mean_counter(cal_fetch, "FETCH_SIZE", "copyBuffer")
+    cw, _ = _mean_counter(cal_write, "WRITE_SIZE", "copyBuffer")
+    gib_kib = float(1 << 20)
+    fs, ws = gib_kib / cf, gib_kib / cw
+    line = [ln for ln in open(bench_json).read().splitlines() if ln.startswith("{")][-1]
+    algo = json.loads(line)["roofline"]["bytes_per_launch"]
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha256()
+    for f in ("fe_kernels.hip", "fe_internal.hpp", "fe_device.hpp"):
+        h.update(open(os.path.join(src, f), "rb").read())
+    return json.dumps({"kernel": kernel, "workload": workload, "dispatches": [nf, nw], "fetch_kib_mean": f_kib,
+                       "write_kib_mean": w_kib, "fetch_scale": fs, "write_scale": ws,
+                       "traffic_bytes_per_launch": 1024.0 * (f_kib * fs + w_kib * ws),
+                       "algorithmic_bytes_per_launch": algo, "source_sha256": h.hexdigest()}, indent=1)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("mode", choices=["trace", "pmc"])
-    ap.add_argument("dir")
+    ap.add_argument("mode", choices=["trace", "pmc", "traffic"])
+    ap.add_argument("dir", nargs="?")
     ap.add_argument("--min-ns", type=float, default=0.0)
     ap.add_argument("--top", type=int, default=12)
     ap.add_argument("--kernel", default="")
+    for opt in ("--fetch", "--write", "--cal-fetch", "--cal-write", "--bench-json", "--workload"):
+        ap.add_argument(opt)
     a = ap.parse_args(argv)
-    print(trace(a.dir, a.min_ns, a.top) if a.mode == "trace" else pmc(a.dir, a.kernel))
+    if a.mode == "traffic":
+        print(traffic(a.fetch, a.write, a.cal_fetch, a.cal_write, a.bench_json, a.kernel, a.workload))
+    else:
+        print(trace(a.dir, a.min_ns, a.top) if a.mode == "trace" else pmc(a.dir, a.kernel))
 
 
 if __name__ == "__main__":
