@@ -177,7 +177,8 @@ __device__ __forceinline__ void push_back(const T Px[2][2][3], const T Py[2][2][
 
 // ---------------------------------------------------------------------------
 // Single-reduction CG, staging of a brick's nodes for launch j (see ElemArgs): every lane
-// first issues the loads of all its dofs, then forms
+// requests the previous launch's slot sums, then the loads of all its dofs (vector loads return
+// in order, so the scalar step below waits for the slot sums alone), forms alpha, beta, and then
 //   s_{j-1} = w_{j-1} + beta s_{j-2},  r_j = r_{j-1} - alpha s_{j-1},  u_j = M^-1 r_j
 // (launch 0: r_0 = b, u_0 = M^-1 b).  Every brick that touches a node forms the same u_j; the
 // owner also stores s_{j-1}, r_j, p_{j-1} = u_{j-1} + beta p_{j-2}, x_j = x_{j-1} + alpha p_{j-1},
@@ -185,9 +186,24 @@ __device__ __forceinline__ void push_back(const T Px[2][2][3], const T Py[2][2][
 // u_j goes to s_x (0 on constrained dofs, whose value goes to s_b), s_y is cleared.
 constexpr int STAGE_IT = (NN * 3 + EBLOCK - 1) / EBLOCK;
 
-template <typename T, bool NEED_L>
-__device__ __forceinline__ void cg_stage_brick(const ElemArgs& a, int n, int a0, int b0, int c0, T alpha, T beta,
-                                               T* s_x, double* s_y, T* s_b, T* s_l, double& g, double& rr) {
+template <typename T>
+__device__ __forceinline__ bool cg_scalars(const ElemArgs& a, const double v_in[3], double (*sh)[EBLOCK / 64],
+                                           T& alpha_out, T& beta_out);
+
+template <typename T, bool NEED_L, bool BLK, typename Early>
+__device__ __forceinline__ bool cg_stage_brick(const ElemArgs& a, int n, int a0, int b0, int c0,
+                                               double (*sh)[EBLOCK / 64], T* s_x, double* s_y, T* s_b, T* s_l,
+                                               unsigned char* s_fx, double& g, double& rr, Early&& early) {
+  static_assert(CGS_SLOTS == EBLOCK, "one reduction slot per lane");
+  // the previous launch's slot sums are requested before the staging loads (loads return in
+  // order), so the scalar reduction overlaps the staging traffic
+  double acc_v[3] = {0, 0, 0};
+  const bool prev = a.cg_j > 0;
+  if (prev) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc_v[k] = a.cg_acc_in[k * CGS_SLOTS + threadIdx.x];
+  }
+  T alpha = 0, beta = 0;
   const T* __restrict__ RO = static_cast<const T*>(a.cg_rold);
   const T* __restrict__ WO = static_cast<const T*>(a.cg_wold);
   const T* __restrict__ SO = static_cast<const T*>(a.cg_sold);
@@ -199,7 +215,8 @@ __device__ __forceinline__ void cg_stage_brick(const ElemArgs& a, int n, int a0,
   T* __restrict__ X = static_cast<T*>(a.cg_x);
   T* __restrict__ WZ = static_cast<T*>(a.cg_wzero);
   const unsigned char* __restrict__ mask = a.mask;
-  const bool blk = a.cg_block != 0, first = a.cg_j == 0;
+  constexpr bool blk = BLK;
+  const bool first = a.cg_j == 0;
   const int64_t np1 = n + 1;
   // loads in batches of SB rounds (all loads of a batch, then its updates and stores):
   // FP64 takes all rounds at once, FP32 two batches, which measured faster there
@@ -208,7 +225,8 @@ __device__ __forceinline__ void cg_stage_brick(const ElemArgs& a, int n, int a0,
   for (int t0 = 0; t0 < STAGE_IT; t0 += SB) {
     int64_t dofs[SB];
     int cs[SB];
-    bool in[SB], own[SB], fixed[SB];
+    bool in[SB], own[SB];
+    unsigned char mk[SB];
     T ro[SB][3], wo[SB][3], so[SB][3], m[SB][3], po[SB], xo[SB], lv[SB];
 #pragma unroll
     for (int t = 0; t < SB; ++t) {
@@ -236,19 +254,27 @@ __device__ __forceinline__ void cg_stage_brick(const ElemArgs& a, int n, int a0,
         m[t][0] = in[t] ? mb[i0] : T(0);
         m[t][1] = in[t] ? mb[i1] : T(0);
         m[t][2] = in[t] ? mb[i2] : T(0);
-      } else {
-        m[t][0] = m[t][1] = m[t][2] = in[t] ? M[dof] : T(0);
+      } else {  // (one word: a copy of a register with a load in flight would wait for it)
+        m[t][0] = in[t] ? M[dof] : T(0);
+        m[t][1] = m[t][2] = T(0);
       }
-      fixed[t] = in[t] && mask && mask[dof];
+      mk[t] = mask ? mask[dof] : (unsigned char)0;  // dof is 0 outside the mesh
       po[t] = own[t] && !first ? P[dof] : T(0);
       xo[t] = own[t] && !first ? X[dof] : T(0);
       lv[t] = NEED_L && in[t] ? XL[dof] : T(0);
+    }
+    if (t0 == 0) {
+      early();
+      if (prev && !cg_scalars<T>(a, acc_v, sh, alpha, beta)) return false;
     }
 #pragma unroll
     for (int t = 0; t < SB; ++t) {
       const int i = threadIdx.x + (t0 + t) * EBLOCK;
       if (i >= NN * 3) break;
       const int c = cs[t];
+      int mkv = mk[t];
+      asm volatile("" : "+v"(mkv));  // keeps the flag test here, after every load of the batch was issued
+      const bool fixed = in[t] && mkv != 0;
       T rn[3], sn[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -276,15 +302,17 @@ __device__ __forceinline__ void cg_stage_brick(const ElemArgs& a, int n, int a0,
         g += (double)rn[c] * (double)u;
         rr += (double)rn[c] * (double)rn[c];
       }
-      if (fixed[t]) {
+      if (fixed) {
         s_b[i] = u;
         u = 0;
       }
+      s_fx[i] = fixed ? 1 : 0;
       s_x[i] = in[t] ? u : T(0);
       s_y[i] = 0;
       if (NEED_L) s_l[i] = lv[t];
     }
   }
+  return true;
 }
 
 // Start of single-reduction CG launch j >= 1, run redundantly by every workgroup (no
@@ -297,14 +325,10 @@ __device__ __forceinline__ void cg_stage_brick(const ElemArgs& a, int n, int a0,
 // (g, alpha) of iterate j-1 go to history slot (j-1) & 1 while slot j & 1 is read.
 // Returns false when the iteration stops (every workgroup reaches the same decision).
 template <typename T>
-__device__ __forceinline__ bool cg_scalars(const ElemArgs& a, double (*sh)[EBLOCK / 64], T& alpha_out, T& beta_out) {
+__device__ __forceinline__ bool cg_scalars(const ElemArgs& a, const double v_in[3], double (*sh)[EBLOCK / 64],
+                                           T& alpha_out, T& beta_out) {
   const long j = a.cg_j;
-  const double* acc = a.cg_acc_in;
-  double v[3] = {0, 0, 0};
-  for (int i = threadIdx.x; i < CGS_SLOTS; i += EBLOCK) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) v[k] += acc[k * CGS_SLOTS + i];
-  }
+  double v[3] = {v_in[0], v_in[1], v_in[2]};
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -373,6 +397,7 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
   __shared__ T s_l[NEED_L ? NN * 3 : 1];
   __shared__ T s_b[OP == OP_CG_APPLY ? NN * 3 : 1];  // CG: u on constrained dofs (A u = u there)
   __shared__ double s_red[6][EBLOCK / 64];
+  __shared__ unsigned char s_fx[NN * 3];  // constrained dof flags of the brick (apply_bc)
 
   if (stop && *stop) return;
   const int n = a.n;
@@ -389,51 +414,69 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
   const int tid = threadIdx.x;
   const T* X = static_cast<const T*>(a.x);
   const T* XL = static_cast<const T*>(a.xlin);
-  // single-reduction CG: alpha_{j-1}, beta_{j-1} from the slots of the previous launch
-  T cg_alpha = 0, cg_beta = 0;
-  if (OP == OP_CG_APPLY) {
-    if (blockIdx.x == 0)
-      for (int i = tid; i < 3 * CGS_SLOTS; i += EBLOCK) a.cg_acc_zero[i] = 0.0;  // slots of launch j+1
-    if (a.cg_j > 0 && !cg_scalars<T>(a, s_red, cg_alpha, cg_beta)) return;
-  }
-  double cg_g = 0, cg_rr = 0;  // owners' shares of (r_j, u_j) and ||r_j||^2
-  const int64_t np1 = n + 1;
-
-  if (OP == OP_CG_APPLY) {
-    cg_stage_brick<T, NEED_L>(a, n, a0, b0, c0, cg_alpha, cg_beta, s_x, s_y, s_b, s_l, cg_g, cg_rr);
-  } else {  // all loads of the lane first, then the LDS stores
-    T v[STAGE_IT], vl[STAGE_IT];
-    bool fx[STAGE_IT];
-    const bool bc = APPLY_LIKE && a.apply_bc && a.mask;
-#pragma unroll
-    for (int t = 0; t < STAGE_IT; ++t) {
-      const int i = tid + t * EBLOCK;
-      const int c = i % 3, nd = i / 3;
-      const int li = nd % NX, lj = (nd / NX) % NY, lk = nd / (NX * NY);
-      const int gi = a0 + li, gj = b0 + lj, gk = c0 + lk;
-      const bool in = i < NN * 3 && gi <= n && gj <= n && gk <= n;
-      const int64_t dof = 3 * (gi + np1 * (gj + np1 * gk)) + c;
-      v[t] = in ? X[dof] : T(0);
-      vl[t] = NEED_L && in ? XL[dof] : T(0);
-      fx[t] = bc && in && a.mask[dof];
-    }
-#pragma unroll
-    for (int t = 0; t < STAGE_IT; ++t) {
-      const int i = tid + t * EBLOCK;
-      if (i >= NN * 3) break;
-      s_x[i] = fx[t] ? T(0) : v[t];
-      if (OP != OP_VJP) s_y[i] = 0;
-      if (NEED_L) s_l[i] = vl[t];
-    }
-  }
-  __syncthreads();
-
   const int ex = tid % TX, ey = (tid / TX) % TY, ez = tid / (TX * TY);
   const int ga = a0 + ex, gb = b0 + ey, gc = c0 + ez;
   const bool valid = ga < n && gb < n && gc < n;
   const int64_t e = valid ? (ga + (int64_t)n * (gb + (int64_t)n * gc)) : 0;
   const int64_t ne = a.n_el;
   const T h = T(a.h), inv_h = T(1.0 / a.h);
+  // the element's phase is requested before the staging loads; the operator's first stored-
+  // tangent word of every Gauss point right after them (both arrive before they are used)
+  const int ph = valid ? (int)a.phase[e] : 0;
+  const T* tang_c = static_cast<const T*>(a.tangent);
+  T tq0[8];
+  auto early = [&]() {
+    if (APPLY_LIKE && MS == MS_J2) {
+      const bool j2 = valid && a.mat.ph[ph].model == FE_J2;
+#pragma unroll
+      for (int qq = 0; qq < 8; ++qq) tq0[qq] = j2 ? tang_c[(int64_t)qq * ne + e] : T(-1);
+    }
+  };
+
+  double cg_g = 0, cg_rr = 0;  // owners' shares of (r_j, u_j) and ||r_j||^2
+  const int64_t np1 = n + 1;
+
+  if (OP == OP_CG_APPLY) {
+    if (blockIdx.x == 0)
+      for (int i = tid; i < 3 * CGS_SLOTS; i += EBLOCK) a.cg_acc_zero[i] = 0.0;  // slots of launch j+1
+    // (one instance per preconditioner form, so each staging path is branch-free)
+    const bool go =
+        a.cg_block
+            ? cg_stage_brick<T, NEED_L, true>(a, n, a0, b0, c0, s_red, s_x, s_y, s_b, s_l, s_fx, cg_g, cg_rr, early)
+            : cg_stage_brick<T, NEED_L, false>(a, n, a0, b0, c0, s_red, s_x, s_y, s_b, s_l, s_fx, cg_g, cg_rr, early);
+    if (!go) return;
+  } else {  // all loads of the lane first, then the LDS stores
+    T v[STAGE_IT], vl[STAGE_IT];
+    unsigned char mk[STAGE_IT];
+    bool in[STAGE_IT];
+    const bool bc = a.apply_bc && a.mask;
+#pragma unroll
+    for (int t = 0; t < STAGE_IT; ++t) {
+      const int i = tid + t * EBLOCK;
+      const int c = i % 3, nd = i / 3;
+      const int li = nd % NX, lj = (nd / NX) % NY, lk = nd / (NX * NY);
+      const int gi = a0 + li, gj = b0 + lj, gk = c0 + lk;
+      in[t] = i < NN * 3 && gi <= n && gj <= n && gk <= n;
+      const int64_t dof = in[t] ? 3 * (gi + np1 * (gj + np1 * gk)) + c : 0;
+      v[t] = in[t] ? X[dof] : T(0);
+      vl[t] = NEED_L && in[t] ? XL[dof] : T(0);
+      mk[t] = bc ? a.mask[dof] : (unsigned char)0;
+    }
+    early();
+#pragma unroll
+    for (int t = 0; t < STAGE_IT; ++t) {
+      const int i = tid + t * EBLOCK;
+      if (i >= NN * 3) break;
+      int mkv = mk[t];
+      asm volatile("" : "+v"(mkv));  // (the flag test stays here, see cg_stage_brick)
+      const bool fx = in[t] && mkv != 0;
+      s_fx[i] = fx ? 1 : 0;
+      s_x[i] = (APPLY_LIKE && fx) ? T(0) : v[t];
+      if (OP != OP_VJP) s_y[i] = 0;
+      if (NEED_L) s_l[i] = vl[t];
+    }
+  }
+  __syncthreads();
 
   T Fo[2][2][2][3];
 #pragma unroll
@@ -447,7 +490,6 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
   double ssum[6] = {0, 0, 0, 0, 0, 0};
 
   if (valid) {
-    const int ph = a.phase[e];
     const PhaseConst pc = a.mat.ph[ph];
     const T sc = (a.scale && OP != OP_VJP) ? static_cast<const T*>(a.scale)[e] : T(1);
     const T lam = T(pc.lam) * sc, mu = T(pc.mu) * sc;
@@ -488,20 +530,18 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
 #pragma unroll
         for (int c = 0; c < 3; ++c) Px[x][y][c] = Py[x][y][c] = Pz[x][y][c] = 0;
 
-    // J2 operator: the first stored-tangent word of every Gauss point is requested up front,
-    // the five plastic-point words of the next point while the current one is computed
-    const T* tang_c = static_cast<const T*>(a.tangent);
-    T tq0[8];
-    if (APPLY_LIKE && MS == MS_J2) {
-#pragma unroll
-      for (int qq = 0; qq < 8; ++qq) tq0[qq] = pc.model == FE_J2 ? tang_c[(int64_t)qq * ne + e] : T(-1);
-    }
-    T pw[2][5];
+    // J2 operator: the first stored-tangent word of every Gauss point arrived with the staging
+    // (tq0); the five plastic-point words are requested PF Gauss points ahead of their use (a
+    // ring of PF + 1 register sets: 2 measured best, 3 costs more registers than it hides)
+    constexpr int PF = 2;
+    T pw[PF + 1][5];
     auto load_pw = [&](int qp, T* w) {
 #pragma unroll
       for (int k = 1; k < 6; ++k) w[k - 1] = tq0[qp] >= 0 ? tang_c[(int64_t)(k * 8 + qp) * ne + e] : T(0);
     };
-    if (APPLY_LIKE && MS == MS_J2) load_pw(0, pw[0]);
+    if (APPLY_LIKE && MS == MS_J2)
+#pragma unroll
+      for (int q0 = 0; q0 < PF; ++q0) load_pw(q0, pw[q0]);
     const T* st_in = static_cast<const T*>(a.state_in);
     T* st_out = static_cast<T*>(a.state_out);
     T* tang = static_cast<T*>(a.tangent);
@@ -513,7 +553,7 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
           const int qp = p + 2 * q + 4 * r;
-          if (APPLY_LIKE && MS == MS_J2 && qp < 7) load_pw(qp + 1, pw[(qp + 1) & 1]);
+          if (APPLY_LIKE && MS == MS_J2 && qp + PF < 8) load_pw(qp + PF, pw[(qp + PF) % (PF + 1)]);
           T H[3][3], S[3][3];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
@@ -594,7 +634,7 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
                 general_apply(H, static_cast<const float*>(a.sur_D) + (int64_t)slot * 36, S);
               } else {
 #pragma unroll
-                for (int k = 1; k < 6; ++k) tn[k] = pw[qp & 1][k - 1];
+                for (int k = 1; k < 6; ++k) tn[k] = pw[qp % (PF + 1)][k - 1];
                 j2_tangent_coeffs(tn, Kb, Gs, Hh, lp, mp, beta, N);
                 j2_apply(H, lp, mp, beta, N, S);
               }
@@ -760,7 +800,10 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
 
   T* Y = static_cast<T*>(a.y);
   if (!Y) return;
-  for (int i = tid; i < NN * 3; i += EBLOCK) {
+#pragma unroll 1  // (unrolled, the instance spills)
+  for (int t = 0; t < STAGE_IT; ++t) {
+    const int i = tid + t * EBLOCK;
+    if (i >= NN * 3) break;
     const int c = i % 3, nd = i / 3;
     const int li = nd % NX, lj = (nd / NX) % NY, lk = nd / (NX * NY);
     const int gi = a0 + li, gj = b0 + lj, gk = c0 + lk;
@@ -769,7 +812,7 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
     const bool own = (min(gi, n - 1) - a0 < TX) && (min(gj, n - 1) - b0 < TY) && (min(gk, n - 1) - c0 < TZ);
     const bool priv = (gi == 0 || li >= 1) && (gi == n || li < TX) && (gj == 0 || lj >= 1) && (gj == n || lj < TY) &&
                       (gk == 0 || lk >= 1) && (gk == n || lk < TZ);
-    if (a.apply_bc && a.mask && a.mask[dof]) {
+    if (s_fx[i]) {
       if (own) {
         if (OP == OP_CG_APPLY) {  // A u = u on constrained dofs; their (u, A u) share is u^2
           const T v = s_b[i];
@@ -787,10 +830,23 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
       atomic_add(Y + dof, T(s_y[i]));
   }
   if (OP == OP_CG_APPLY) {  // partials of (u_j, A u_j), (r_j, u_j), ||r_j||^2
-    const double t0 = block_sum(pq, &s_red[0][0]);
-    const double t1 = block_sum(cg_g, &s_red[0][0]);
-    const double t2 = block_sum(cg_rr, &s_red[0][0]);
+    double q3[3] = {pq, cg_g, cg_rr};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) q3[k] += __shfl_down(q3[k], off, 64);
+    }
+    if ((tid & 63) == 0)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s_red[3 + k][tid >> 6] = q3[k];
+    __syncthreads();
     if (threadIdx.x == 0) {  // workgroups share CGS_SLOTS slots per quantity
+      double t0 = 0, t1 = 0, t2 = 0;
+      for (int w = 0; w < EBLOCK / 64; ++w) {
+        t0 += s_red[3][w];
+        t1 += s_red[4][w];
+        t2 += s_red[5][w];
+      }
       const int sl = (int)(blockIdx.x % CGS_SLOTS);
       atomic_add(a.cg_acc_out + sl, t0);
       atomic_add(a.cg_acc_out + CGS_SLOTS + sl, t1);
