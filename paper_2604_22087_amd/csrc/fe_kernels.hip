@@ -1131,9 +1131,189 @@ __global__ __launch_bounds__(TAN_BLOCK) void tangent_csr_kernel(TanArgs a, T* va
   }
 }
 
+// CSR values, small-strain models (linear, J2 and the surrogate's Voigt tangents): a workgroup
+// takes TR_NODES consecutive nodes of one x-row of nodes, whose CSR rows are one contiguous
+// segment.  Phase 1 forms the Gauss-point coefficients (lp, mp, beta, N) of the elements
+// around the tile once into LDS.  Phase 2: lane (node, task), one wave per node; the 64 tasks
+// of a node are the (neighbour, shared element) pairs: per axis the neighbour offset d and the
+// element offset o (element = node + o) take (d, o) = (-1, -1), (0, -1), (0, 0) or (1, 0), so
+// 4^3 tasks cover the 27 neighbours with their 1, 2, 4 or 8 shared elements; each lane sums
+// its element's 3x3 block over the 8 Gauss points.  Phase 3 writes the tile's rows in order,
+// each entry the fixed-order sum of its neighbour's tasks (deterministic, no atomics).
+constexpr int TR_NODES = 4;
+constexpr int TR_SETS = (TR_NODES + 1) * 2 * 2 * 8;  // (element, Gauss point) coefficient sets
+
+template <typename T, int MS>
+__global__ __launch_bounds__(256) void tangent_rows_kernel(TanArgs a, T* vals, int apply_bc) {
+  __shared__ T s_co[9][TR_SETS];  // lp, mp, beta, N (xx yy zz yz xz xy); component-major
+  __shared__ int s_sur[TR_SETS];  // surrogate points: slot of their Voigt tangent, else -1
+  __shared__ T s_part[9][256];    // each task's 3x3 block, component-major (conflict-free)
+  __shared__ uint8_t s_mk[3][3][TR_NODES + 2][3];  // constrained flags of the tile's nodes and neighbours
+  const int n = a.n;
+  const int64_t np1 = n + 1, ne = a.n_el;
+  const int tiles_x = (n + TR_NODES) / TR_NODES;  // ceil((n + 1) / TR_NODES)
+  const int64_t nrow = (int64_t)blockIdx.x / tiles_x;
+  const int i0 = (int)(blockIdx.x % tiles_x) * TR_NODES;
+  const int j = (int)(nrow % np1), k = (int)(nrow / np1);
+  const int tid = threadIdx.x;
+  const T inv_h = T(1.0 / a.h), w = T(0.125 * a.h * a.h * a.h);
+
+  // phase 1: elements (i0 - 1 .. i0 + TR_NODES - 1) x (j - 1, j) x (k - 1, k), all 8 points
+  for (int si = tid; si < TR_SETS; si += 256) {
+    const int qp = si & 7, el = si >> 3;
+    const int xl = el % (TR_NODES + 1), yl = (el / (TR_NODES + 1)) & 1, zl = el / (2 * (TR_NODES + 1));
+    const int ea = i0 - 1 + xl, eb = j - 1 + yl, ec = k - 1 + zl;
+    T co[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int sur = -1;
+    if (ea >= 0 && ea < n && eb >= 0 && eb < n && ec >= 0 && ec < n) {
+      const int64_t e = ea + (int64_t)n * (eb + (int64_t)n * ec);
+      const PhaseConst pc = a.mat.ph[a.phase[e]];
+      const T sc = a.scale ? static_cast<const T*>(a.scale)[e] : T(1);
+      co[0] = T(pc.lam) * sc;
+      co[1] = T(pc.mu) * sc;
+      if (MS == MS_J2 && pc.model == FE_J2) {
+        const T* tg = static_cast<const T*>(a.tangent);
+        T tn[6], N[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) tn[q] = tg[(int64_t)(q * 8 + qp) * ne + e];
+        if (tn[0] < T(-1.5)) {
+          sur = a.sur_map[(int64_t)qp * ne + e];
+        } else {
+          j2_tangent_coeffs(tn, T(pc.K) * sc, T(pc.G) * sc, T(pc.H), co[0], co[1], co[2], N);
+#pragma unroll
+          for (int q = 0; q < 6; ++q) co[3 + q] = N[q];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s_co[q][si] = co[q];
+    s_sur[si] = sur;
+  }
+  if (tid < 27 * (TR_NODES + 2)) {  // nodes (i0 - 1 .. i0 + TR_NODES) x (j - 1 .. j + 1) x (k - 1 .. k + 1)
+    const int c = tid % 3, xl = (tid / 3) % (TR_NODES + 2), yl = (tid / (3 * (TR_NODES + 2))) % 3,
+              zl = tid / (9 * (TR_NODES + 2));
+    const int gx = i0 - 1 + xl, gy = j - 1 + yl, gz = k - 1 + zl;
+    const bool in = apply_bc && a.mask && gx >= 0 && gx <= n && gy >= 0 && gy <= n && gz >= 0 && gz <= n;
+    s_mk[zl][yl][xl][c] = in ? a.mask[3 * (gx + np1 * (gy + np1 * (int64_t)gz)) + c] : (uint8_t)0;
+  }
+  __syncthreads();
+
+  // phase 2: one task per lane
+  const int nl = tid >> 6, task = tid & 63;
+  const int i = i0 + nl;
+  const int tx = task & 3, ty = (task >> 2) & 3, tz = task >> 4;
+  const int dx = tx == 0 ? -1 : (tx == 3 ? 1 : 0), dy = ty == 0 ? -1 : (ty == 3 ? 1 : 0),
+            dz = tz == 0 ? -1 : (tz == 3 ? 1 : 0);
+  const int ox = tx <= 1 ? -1 : 0, oy = ty <= 1 ? -1 : 0, oz = tz <= 1 ? -1 : 0;
+  const int ea = i + ox, eb = j + oy, ec = k + oz;
+  T B[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  if (i <= n && ea >= 0 && ea < n && eb >= 0 && eb < n && ec >= 0 && ec < n) {
+    const int sb = (((oz + 1) * 2 + (oy + 1)) * (TR_NODES + 1) + (nl + ox + 1)) * 8;
+#pragma unroll
+    for (int qp = 0; qp < 8; ++qp) {
+      const int p = qp & 1, q = (qp >> 1) & 1, r = qp >> 2;
+      T ga[3], gb[3];
+      basis_grad(-ox, -oy, -oz, p, q, r, inv_h, ga);               // the row node's corner
+      basis_grad(dx - ox, dy - oy, dz - oz, p, q, r, inv_h, gb);   // the neighbour's corner
+      T co[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) co[q] = s_co[q][sb + qp];
+      const int sur = MS == MS_J2 ? s_sur[sb + qp] : -1;
+      if (sur >= 0) {
+        QpTangent<T> t;
+        t.kind = 2;
+        t.D = static_cast<const float*>(a.sur_D) + (int64_t)sur * 36;
+        block_add(t, ga, gb, w, B);
+      } else {
+        // w (lp ga gb^T + mp (ga.gb I + gb ga^T) - beta (N ga)(N gb)^T), three FMAs an entry
+        const T wl = w * co[0], wm = w * co[1];
+        const T u[3] = {wl * ga[0], wl * ga[1], wl * ga[2]}, v[3] = {wm * ga[0], wm * ga[1], wm * ga[2]};
+        const T t = v[0] * gb[0] + v[1] * gb[1] + v[2] * gb[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          B[c][c] += t;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) B[c][d] += u[c] * gb[d] + v[d] * gb[c];
+        }
+        if (MS == MS_J2 && co[2] != T(0)) {  // (a wave skips it when its elements are elastic there)
+          const T wb = w * co[2];
+          const T na[3] = {wb * (co[3] * ga[0] + co[8] * ga[1] + co[7] * ga[2]),
+                           wb * (co[8] * ga[0] + co[4] * ga[1] + co[6] * ga[2]),
+                           wb * (co[7] * ga[0] + co[6] * ga[1] + co[5] * ga[2])};
+          const T nb[3] = {co[3] * gb[0] + co[8] * gb[1] + co[7] * gb[2], co[8] * gb[0] + co[4] * gb[1] + co[6] * gb[2],
+                           co[7] * gb[0] + co[6] * gb[1] + co[5] * gb[2]};
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) B[c][d] -= na[c] * nb[d];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s_part[3 * c + d][tid] = B[c][d];
+  __syncthreads();
+
+  // phase 3: one lane per (node, neighbour) block: the fixed-order sum of the neighbour's tasks,
+  // written as three column triplets into the node's three rows (the tile's rows are one
+  // contiguous segment of the CSR values, neighbours in rank order inside each row)
+  const int cy = axis_cnt(j, n), cz = axis_cnt(k, n);
+  if (tid < 27 * TR_NODES) {
+    const int m = tid / 27, nb = tid - 27 * m;
+    const int ii = i0 + m;
+    const int ddx = nb % 3 - 1, ddy = (nb / 3) % 3 - 1, ddz = nb / 9 - 1;
+    const int cx = ii <= n ? axis_cnt(ii, n) : 0;
+    if (ii <= n && ii + ddx >= 0 && ii + ddx <= n && j + ddy >= 0 && j + ddy <= n && k + ddz >= 0 &&
+        k + ddz <= n) {
+      const int len = 3 * cx * cy * cz;
+      const int rank = (axis_rank(k, ddz) * cy + axis_rank(j, ddy)) * cx + axis_rank(ii, ddx);
+      // the neighbour's tasks per axis: d = -1 -> task 0, d = 0 -> tasks 1, 2, d = 1 -> task 3
+      const int ax0 = ddx < 0 ? 0 : (ddx == 0 ? 1 : 3), ax1 = ddx == 0 ? 2 : ax0;
+      const int ay0 = ddy < 0 ? 0 : (ddy == 0 ? 1 : 3), ay1 = ddy == 0 ? 2 : ay0;
+      const int az0 = ddz < 0 ? 0 : (ddz == 0 ? 1 : 3), az1 = ddz == 0 ? 2 : az0;
+      T v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      for (int zz = az0; zz <= az1; ++zz)
+        for (int yy = ay0; yy <= ay1; ++yy)
+          for (int xx = ax0; xx <= ax1; ++xx) {
+            const int tk = m * 64 + xx + 4 * yy + 16 * zz;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) v[q] += s_part[q][tk];
+          }
+      const bool self = ddx == 0 && ddy == 0 && ddz == 0;
+      T* out = vals + node_row_start(ii, j, k, n) + 3 * rank;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          T x = v[3 * c + d];
+          if (s_mk[1][1][m + 1][c] || s_mk[1 + ddz][1 + ddy][m + 1 + ddx][d]) x = (self && c == d) ? T(1) : T(0);
+          out[(int64_t)c * len + d] = x;
+        }
+    }
+  }
+}
+
 hipError_t launch_tangent_csr(const fe_problem* p, void* vals, int apply_bc, hipStream_t s) {
   if (p->general) return gen_tangent(p, vals, apply_bc, tan_args(p), s);
   const TanArgs a = tan_args(p);
+  if (p->model_set != MS_NH) {
+    const int64_t np1 = p->n + 1;
+    const dim3 rgrid((unsigned)(np1 * np1 * ((np1 + TR_NODES - 1) / TR_NODES))), rblock(256);
+    if (p->prec == FE_F64) {
+      if (p->model_set == MS_J2)
+        timed_launch((tangent_rows_kernel<double, MS_J2>), rgrid, rblock, 0, s, a, (double*)vals, apply_bc);
+      else
+        timed_launch((tangent_rows_kernel<double, MS_LINEAR>), rgrid, rblock, 0, s, a, (double*)vals, apply_bc);
+    } else {
+      if (p->model_set == MS_J2)
+        timed_launch((tangent_rows_kernel<float, MS_J2>), rgrid, rblock, 0, s, a, (float*)vals, apply_bc);
+      else
+        timed_launch((tangent_rows_kernel<float, MS_LINEAR>), rgrid, rblock, 0, s, a, (float*)vals, apply_bc);
+    }
+    return hipGetLastError();
+  }
   const dim3 grid((unsigned)((p->n_nodes + TAN_NODES - 1) / TAN_NODES)), block(TAN_BLOCK);
   if (p->prec == FE_F64) {
     double* v = (double*)vals;
