@@ -1149,6 +1149,7 @@ __global__ __launch_bounds__(256) void tangent_rows_kernel(TanArgs a, T* vals, i
   __shared__ int s_sur[TR_SETS];  // surrogate points: slot of their Voigt tangent, else -1
   __shared__ T s_part[9][256];    // each task's 3x3 block, component-major (conflict-free)
   __shared__ uint8_t s_mk[3][3][TR_NODES + 2][3];  // constrained flags of the tile's nodes and neighbours
+  __shared__ uint8_t s_uni[TR_SETS / 8];           // element with one isotropic (lp, mp) at all 8 points
   const int n = a.n;
   const int64_t np1 = n + 1, ne = a.n_el;
   const int tiles_x = (n + TR_NODES) / TR_NODES;  // ceil((n + 1) / TR_NODES)
@@ -1159,13 +1160,15 @@ __global__ __launch_bounds__(256) void tangent_rows_kernel(TanArgs a, T* vals, i
   const T inv_h = T(1.0 / a.h), w = T(0.125 * a.h * a.h * a.h);
 
   // phase 1: elements (i0 - 1 .. i0 + TR_NODES - 1) x (j - 1, j) x (k - 1, k), all 8 points
-  for (int si = tid; si < TR_SETS; si += 256) {
+  static_assert(TR_SETS <= 256, "one coefficient set per lane");
+  {
+    const int si = tid;
     const int qp = si & 7, el = si >> 3;
     const int xl = el % (TR_NODES + 1), yl = (el / (TR_NODES + 1)) & 1, zl = el / (2 * (TR_NODES + 1));
     const int ea = i0 - 1 + xl, eb = j - 1 + yl, ec = k - 1 + zl;
     T co[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     int sur = -1;
-    if (ea >= 0 && ea < n && eb >= 0 && eb < n && ec >= 0 && ec < n) {
+    if (si < TR_SETS && ea >= 0 && ea < n && eb >= 0 && eb < n && ec >= 0 && ec < n) {
       const int64_t e = ea + (int64_t)n * (eb + (int64_t)n * ec);
       const PhaseConst pc = a.mat.ph[a.phase[e]];
       const T sc = a.scale ? static_cast<const T*>(a.scale)[e] : T(1);
@@ -1185,9 +1188,17 @@ __global__ __launch_bounds__(256) void tangent_rows_kernel(TanArgs a, T* vals, i
         }
       }
     }
+    // an element whose 8 points share lp, mp and have no plastic or surrogate term is summed in
+    // closed form in phase 2 (the 8 lanes of an element are one aligned group of a wave)
+    const T lp0 = __shfl(co[0], tid & ~7, 64), mp0 = __shfl(co[1], tid & ~7, 64);
+    const bool iso = si < TR_SETS && co[2] == T(0) && sur < 0 && co[0] == lp0 && co[1] == mp0;
+    const unsigned long long bal = __ballot(iso);
+    if (si < TR_SETS) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) s_co[q][si] = co[q];
-    s_sur[si] = sur;
+      for (int q = 0; q < 9; ++q) s_co[q][si] = co[q];
+      s_sur[si] = sur;
+      if ((si & 7) == 0) s_uni[si >> 3] = ((bal >> (tid & 63 & ~7)) & 0xffull) == 0xffull ? 1 : 0;
+    }
   }
   if (tid < 27 * (TR_NODES + 2)) {  // nodes (i0 - 1 .. i0 + TR_NODES) x (j - 1 .. j + 1) x (k - 1 .. k + 1)
     const int c = tid % 3, xl = (tid / 3) % (TR_NODES + 2), yl = (tid / (3 * (TR_NODES + 2))) % 3,
@@ -1207,8 +1218,35 @@ __global__ __launch_bounds__(256) void tangent_rows_kernel(TanArgs a, T* vals, i
   const int ox = tx <= 1 ? -1 : 0, oy = ty <= 1 ? -1 : 0, oz = tz <= 1 ? -1 : 0;
   const int ea = i + ox, eb = j + oy, ec = k + oz;
   T B[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  if (i <= n && ea >= 0 && ea < n && eb >= 0 && eb < n && ec >= 0 && ec < n) {
-    const int sb = (((oz + 1) * 2 + (oy + 1)) * (TR_NODES + 1) + (nl + ox + 1)) * 8;
+  const int sb = (((oz + 1) * 2 + (oy + 1)) * (TR_NODES + 1) + (nl + ox + 1)) * 8;
+  const bool task_ok = i <= n && ea >= 0 && ea < n && eb >= 0 && eb < n && ec >= 0 && ec < n;
+  if (task_ok && s_uni[sb >> 3]) {
+    // sum over the 8 points in closed form: with A = sum_q w ga gb^T (geometry only),
+    // B = lp A + mp (tr(A) I + A^T); per axis the Gauss sums of the two corners' 1-D factors are
+    // S = sum_p phi_a(g_p) phi_b(g_p) (GA^2 + GB^2 on equal corners, 2 GA GB otherwise) and
+    // sum_p phi(g_p) = 1, the derivative factors are +-1/h
+    const T lp = s_co[0][sb], mp = s_co[1][sb];
+    const int ca[3] = {-ox, -oy, -oz}, cb[3] = {dx - ox, dy - oy, dz - oz};
+    T sg[3], S[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      sg[c] = (ca[c] == cb[c] ? inv_h : -inv_h) * inv_h;  // s_a s_b
+      S[c] = ca[c] == cb[c] ? T(GA * GA + GB * GB) : T(2 * GA * GB);
+    }
+    const T sa[3] = {ca[0] ? inv_h : -inv_h, ca[1] ? inv_h : -inv_h, ca[2] ? inv_h : -inv_h};
+    const T sbv[3] = {cb[0] ? inv_h : -inv_h, cb[1] ? inv_h : -inv_h, cb[2] ? inv_h : -inv_h};
+    T A[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        A[c][d] = c == d ? w * 2 * sg[c] * S[(c + 1) % 3] * S[(c + 2) % 3] : w * sa[c] * sbv[d] * S[3 - c - d];
+    const T tr = mp * (A[0][0] + A[1][1] + A[2][2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) B[c][d] = lp * A[c][d] + mp * A[d][c] + (c == d ? tr : T(0));
+  } else if (task_ok) {
 #pragma unroll
     for (int qp = 0; qp < 8; ++qp) {
       const int p = qp & 1, q = (qp >> 1) & 1, r = qp >> 2;
