@@ -132,6 +132,39 @@ def test_surrogate_consume_matches_oracle():
     assert flips <= 0.01 * stats["listed"] + 1
 
 
+def test_surrogate_tangent_csr_matches_operator():
+    """At a linearisation with accepted surrogate points, the assembled CSR tangent (each such
+    point's stored Voigt tangent through the element's node-pair blocks) applied to a vector
+    equals the matrix-free operator (the same tangent applied to the Gauss-point strain), at
+    every dof: the two kernels read the same FP32 tangents and differ only in summation order."""
+    import torch
+    from paper_2604_22087_amd import surrogate as gsur
+    n = 6
+    rve, u, st, P = _setup(n)
+    cap = 8 * n ** 3
+    x = torch.empty(cap, 13, dtype=torch.float32, device="cuda")
+    y = torch.empty(cap, 6, dtype=torch.float32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    s_in = torch.tensor(state_to_lib(st["eps_p"], st["alpha"]), device="cuda")
+    ut = torch.tensor(u, device="cuda")
+    P.set_capture(x, y, count, stride=1)
+    P.residual(ut, s_in)
+    P.set_capture(None)
+    m = int(count.item())
+    W, _ = gsur.train(x[:m].contiguous(), y[:m].contiguous(), epochs=40, batch=256, lr=3e-3)
+    P.set_surrogate(W, fallback_tol=0.5)  # accept most points: this test is about the tangent path
+    rp, ci = P.csr_indices()
+    vals = P.tangent_csr(ut, s_in)
+    stats = P.surrogate_stats()
+    assert stats["accepted"] > 0
+    v = torch.randn(P.n_dof, dtype=torch.float64, device="cuda", generator=torch.Generator(device="cuda").manual_seed(3))
+    y_csr = P.apply_csr(rp, ci, vals, v)
+    y_mf = P.apply_matfree(v)
+    err = float((y_csr - y_mf).abs().max() / y_mf.abs().max())
+    print(f"  accepted {stats['accepted']} of {stats['listed']}, max rel diff {err:.2e}", flush=True)
+    assert err <= 1e-12
+
+
 def test_surrogate_newton_end_to_end():
     """Train on return-map samples of a small fiber RVE, then drive a Newton ramp with the
     network: the ramp converges and its homogenised stress stays within 1e-3 of the
