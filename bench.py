@@ -607,6 +607,22 @@ def main():
                        "pcg_iterations": info32["pcg_iterations"],
                        "operators": operator_rates(P32, u32, s32)}
         del P32
+        # the same ramp with the nodal sums in FP32 as well (default: FP64 sums in FP32 problems)
+        P32, _ = setup(n, "f32")
+        P32.set_fp32_accumulation(True)
+        u32, s32 = P32.vector(), P32.state()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, _, sig32, info32 = run_ramp(P32, u32, s32, path)
+        torch.cuda.synchronize()
+        t32 = time.perf_counter() - t1
+        s32a = np.array([s[0] for s in sig32])
+        out["fp32"]["fp32_nodal_sums"] = {
+            "value": P32.n_dof * info32["operator_applies"] / t32 / 1e9, "ms_per_step": 1e3 * t32,
+            "sigma_bar_xx_max_rel_err_vs_f64": float(np.max(np.abs(s32a - s64) / np.abs(s64))),
+            "u_rel_err_vs_f64": float(torch.linalg.norm(u32.double() - u) / torch.linalg.norm(u)),
+            "pcg_iterations": info32["pcg_iterations"]}
+        del P32
     if args.surrogate:
         print(f"[bench] surrogate leg {args.surrogate}^3", file=sys.stderr, flush=True)
         out["surrogate"] = _leg(surrogate_leg, args.surrogate)

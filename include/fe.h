@@ -325,6 +325,14 @@ int fe_newton(fe_problem* p, const double* load_path_host, int n_steps, const fe
  * FE_ERR_ARG.  on = 0 returns to the default (faster) mode. */
 int fe_set_deterministic(fe_problem* p, int on);
 
+/* FP32 accumulation (on = 1) of an FP32 structured problem (an extension: the paper computes
+ * in FP64).  By default FP32 problems store and compute in FP32 but sum each node's element
+ * forces (residual R(u), K x of Sec. II-A) in FP64 inside the workgroup; with on = 1 those
+ * sums run in FP32 as well, so every nodal value is formed in FP32.  Reductions that decide
+ * convergence (PCG dots, residual norms, the Newton test) stay FP64 either way.  FP64
+ * problems and general meshes: FE_ERR_ARG.  on = 0 returns to FP64 nodal sums. */
+int fe_set_fp32_accumulation(fe_problem* p, int on);
+
 /* Commit the plastic history of a converged load step (the state update that ends
  * each Newton solve of Sec. II-A / V-A): state = state_trial, both real [7][8][n_el]
  * (the trial state written by fe_residual's state_out).  For callers that drive

@@ -546,6 +546,14 @@ int fe_set_deterministic(fe_problem* p, int on) {
   return FE_OK;
 }
 
+int fe_set_fp32_accumulation(fe_problem* p, int on) {
+  CHKP(p);
+  if (on && p->prec != FE_F32) return arg_error("FP32 accumulation applies to FP32 problems");
+  if (on && p->general) return arg_error("FP32 accumulation is available on structured problems");
+  p->acc32 = on ? 1 : 0;
+  return FE_OK;
+}
+
 int fe_commit_state(fe_problem* p, const void* state_trial, void* state, void* stream) {
   CHKP(p);
   if (!state_trial || !state) return arg_error("state_trial and state are required");

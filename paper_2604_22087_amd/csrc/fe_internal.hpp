@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdint>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -216,6 +217,7 @@ struct fe_problem {
   void* w_v2 = nullptr;       // scratch vector (Newton)
   void* w_uprev = nullptr;    // Newton with the extrapolating predictor: the converged u two steps back
   int deterministic = 0;      // fe_set_deterministic: fixed summation orders, no floating-point atomics
+  int acc32 = 0;              // fe_set_fp32_accumulation: FP32 problems sum element forces in FP32
   void* w_elf = nullptr;      // deterministic mode: element nodal forces [24][n_el]
   double* stress_part = nullptr;  // deterministic mode: per-workgroup stress partials [elem grid][6]
   void* w_state = nullptr;    // J2 trial state (Newton)

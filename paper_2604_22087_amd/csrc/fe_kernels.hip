@@ -190,9 +190,9 @@ template <typename T>
 __device__ __forceinline__ bool cg_scalars(const ElemArgs& a, const double v_in[3], double (*sh)[EBLOCK / 64],
                                            T& alpha_out, T& beta_out);
 
-template <typename T, bool NEED_L, bool BLK, typename Early>
+template <typename T, bool NEED_L, bool BLK, typename Acc, typename Early>
 __device__ __forceinline__ bool cg_stage_brick(const ElemArgs& a, int n, int a0, int b0, int c0,
-                                               double (*sh)[EBLOCK / 64], T* s_x, double* s_y, T* s_b, T* s_l,
+                                               double (*sh)[EBLOCK / 64], T* s_x, Acc* s_y, T* s_b, T* s_l,
                                                unsigned char* s_fx, double& g, double& rr, Early&& early) {
   static_assert(CGS_SLOTS == EBLOCK, "one reduction slot per lane");
   // the previous launch's slot sums are requested before the staging loads (loads return in
@@ -387,13 +387,17 @@ __device__ __forceinline__ bool cg_scalars(const ElemArgs& a, const double v_in[
 
 // (at least two waves per SIMD: some FP64 instances sit at the 256-register edge, where
 // the allocator would otherwise fall back to one wave per SIMD)
-template <typename T, int OP, int MS>
+// ACC32 (FP32 problems only): the nodal sums accumulate in FP32 LDS as well; by default they
+// are formed in FP64 in both precisions.
+template <typename T, int OP, int MS, bool ACC32 = false>
 __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) void elem_kernel(ElemArgs a,
                                                                                               const int* stop) {
+  static_assert(!ACC32 || sizeof(T) == 4, "FP32 accumulation is an FP32-problem variant");
+  using Acc = typename std::conditional<ACC32, float, double>::type;
   constexpr bool APPLY_LIKE = (OP == OP_APPLY) || (OP == OP_CG_APPLY);
   constexpr bool NEED_L = (OP == OP_VJP) || (APPLY_LIKE && MS == MS_NH);
   __shared__ T s_x[NN * 3];
-  __shared__ double s_y[OP == OP_VJP ? 1 : NN * 3];  // nodal sums, FP64 in both precisions
+  __shared__ Acc s_y[OP == OP_VJP ? 1 : NN * 3];  // nodal sums
   __shared__ T s_l[NEED_L ? NN * 3 : 1];
   __shared__ T s_b[OP == OP_CG_APPLY ? NN * 3 : 1];  // CG: u on constrained dofs (A u = u there)
   __shared__ double s_red[6][EBLOCK / 64];
@@ -788,7 +792,7 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
 #pragma unroll
           for (int c = 0; c < 3; ++c)
             __hip_atomic_fetch_add(&s_y[3 * ((ex + i) + NX * ((ey + j) + NY * (ez + k))) + c],
-                                   (double)Fo[k][j][i][c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                   (Acc)Fo[k][j][i][c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   __syncthreads();
 
@@ -863,6 +867,16 @@ static int elem_grid(int n) {
 template <typename T, int OP>
 static hipError_t launch_elem_t(const fe_problem* p, const ElemArgs& a, const int* stop, hipStream_t s) {
   const dim3 grid(elem_grid(p->n)), block(EBLOCK);
+  if constexpr (sizeof(T) == 4 && OP != OP_VJP) {
+    if (p->acc32) {
+      switch (p->model_set) {
+        case MS_J2: timed_launch((elem_kernel<T, OP, MS_J2, true>), grid, block, 0, s, a, stop); break;
+        case MS_NH: timed_launch((elem_kernel<T, OP, MS_NH, true>), grid, block, 0, s, a, stop); break;
+        default: timed_launch((elem_kernel<T, OP, MS_LINEAR, true>), grid, block, 0, s, a, stop);
+      }
+      return hipGetLastError();
+    }
+  }
   switch (p->model_set) {
     case MS_J2:
       timed_launch((elem_kernel<T, OP, MS_J2>), grid, block, 0, s, a, stop);

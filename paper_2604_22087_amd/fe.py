@@ -55,6 +55,7 @@ SIGNATURES = [
     ("fe_problem_create_hex8", _i32, [ctypes.POINTER(_vp), _i64, _i64, _vp, _vp, _i32, _vp]),
     ("fe_commit_state", _i32, [_vp, _vp, _vp, _vp]),
     ("fe_set_deterministic", _i32, [_vp, _i32]),
+    ("fe_set_fp32_accumulation", _i32, [_vp, _i32]),
     ("fe_problem_destroy", None, [_vp]),
     ("fe_problem_sizes", _i32, [_vp, ctypes.POINTER(_i64)]),
     ("fe_set_materials", _i32, [_vp, _vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_dbl), _vp, _vp]),
@@ -199,6 +200,10 @@ class Problem:
     def set_deterministic(self, on=True):
         """Fixed summation orders (no floating-point atomics) in residual, K*x and diagonal."""
         _check(self.lib.fe_set_deterministic(self.handle, int(bool(on))), "fe_set_deterministic")
+
+    def set_fp32_accumulation(self, on=True):
+        """FP32 problems: sum the element forces at the nodes in FP32 too (default: FP64 sums)."""
+        _check(self.lib.fe_set_fp32_accumulation(self.handle, int(bool(on))), "fe_set_fp32_accumulation")
 
     def commit_state(self, trial, state):
         """state <- trial (the plastic history of a converged step)."""
