@@ -372,12 +372,14 @@ int fe_set_materials(fe_problem* p, const uint8_t* phase, int n_phases, const in
     std::vector<uint8_t> h(p->n_el);
     HIPCHK(hipMemcpyAsync(h.data(), phase, p->n_el, hipMemcpyDeviceToHost, S(stream)));
     HIPCHK(hipStreamSynchronize(S(stream)));
-    int64_t n_j2 = 0;
+    int64_t n_j2 = 0, n_nh = 0;
     for (uint8_t v : h) {
       if (v >= n_phases) return arg_error("phase id >= n_phases");
       n_j2 += models[v] == FE_J2;
+      n_nh += models[v] == FE_NEOHOOKE;
     }
     p->n_j2_el = n_j2;
+    p->n_nh_el = n_nh;
   }
   HIPCHK(hipMemcpyAsync(p->phase, phase, p->n_el, hipMemcpyDeviceToDevice, S(stream)));
   if (scale) {
@@ -1316,7 +1318,9 @@ static int operator_bytes(fe_problem* p, int op, hipStream_t s, double* bytes) {
   double b = 2.0 * w * (double)p->n_dof + (double)p->n_el + w * ((double)st[0] + 5.0 * (double)st[1]);
   if (p->general)  // connectivity and coordinates; all six tangent words of every J2 point
     b = 2.0 * w * (double)p->n_dof + 33.0 * (double)p->n_el + 3.0 * w * (double)p->n_nodes + 6.0 * w * (double)st[0];
-  if (p->model_set == MS_NH) b += w * (double)p->n_dof;  // linearisation point gathered as well
+  if (p->model_set == MS_NH)  // general meshes gather the linearisation point; the cube reads the
+    b += p->general ? w * (double)p->n_dof : 80.0 * w * (double)p->n_nh_el;  // stored F^-T, ln J per point
+  if (p->scale) b += w * (double)p->n_el;  // per-element modulus scale
   *bytes = b;
   return FE_OK;
 }

@@ -233,6 +233,7 @@ struct fe_problem {
   double* host_buf = nullptr;       // pinned scratch
   // learned surrogate (fe_set_surrogate) and sample capture (fe_set_capture)
   int64_t n_j2_el = 0;              // elements of J2 phases
+  int64_t n_nh_el = 0;              // elements of Neo-Hookean phases
   const float* sur_W = nullptr;     // network parameters (caller-owned)
   double sur_tol = 0;
   int sur_full = 0;                 // fe_set_surrogate_tangent

@@ -395,7 +395,7 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
   static_assert(!ACC32 || sizeof(T) == 4, "FP32 accumulation is an FP32-problem variant");
   using Acc = typename std::conditional<ACC32, float, double>::type;
   constexpr bool APPLY_LIKE = (OP == OP_APPLY) || (OP == OP_CG_APPLY);
-  constexpr bool NEED_L = (OP == OP_VJP) || (APPLY_LIKE && MS == MS_NH);
+  constexpr bool NEED_L = OP == OP_VJP;
   __shared__ T s_x[NN * 3];
   __shared__ Acc s_y[OP == OP_VJP ? 1 : NN * 3];  // nodal sums
   __shared__ T s_l[NEED_L ? NN * 3 : 1];
@@ -511,20 +511,15 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
     T Gx[2][2][3], Gy[2][2][3], Gz[2][2][3];
     gradients(U, inv_h, Gx, Gy, Gz);
 
-    // Neo-Hookean APPLY also needs the gradient at the linearisation point
-    T Lx[2][2][3], Ly[2][2][3], Lz[2][2][3];
-    if (APPLY_LIKE && MS == MS_NH) {
+    // Neo-Hookean operator: F^-T and ln J of the linearisation, stored by the residual per
+    // Gauss point ([10][8][n_el]), requested one point ahead of their use
+    T nw[2][10];
+    const bool nh_el = MS == MS_NH && pc.model == FE_NEOHOOKE;
+    auto load_nh = [&](int qp, T* w) {
 #pragma unroll
-      for (int k = 0; k < 2; ++k)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-              U[k][j][i][c] = s_l[3 * ((ex + i) + NX * ((ey + j) + NY * (ez + k))) + c];
-      gradients(U, inv_h, Lx, Ly, Lz);
-    }
+      for (int k = 0; k < 10; ++k) w[k] = nh_el ? tang_c[(int64_t)(k * 8 + qp) * ne + e] : T(0);
+    };
+    if (APPLY_LIKE && MS == MS_NH) load_nh(0, nw[0]);
 
     T Px[2][2][3], Py[2][2][3], Pz[2][2][3];
 #pragma unroll
@@ -558,6 +553,7 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
         for (int p = 0; p < 2; ++p) {
           const int qp = p + 2 * q + 4 * r;
           if (APPLY_LIKE && MS == MS_J2 && qp + PF < 8) load_pw(qp + PF, pw[(qp + PF) % (PF + 1)]);
+          if (APPLY_LIKE && MS == MS_NH && qp < 7) load_nh(qp + 1, nw[(qp + 1) & 1]);
           T H[3][3], S[3][3];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
@@ -647,15 +643,12 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
           }
           if (MS == MS_NH && pc.model == FE_NEOHOOKE) {
             if (APPLY_LIKE) {
-              T H0[3][3], FiT[3][3], lnJ;
+              T FiT[3][3];
 #pragma unroll
-              for (int c = 0; c < 3; ++c) {
-                H0[c][0] = Lx[r][q][c];
-                H0[c][1] = Ly[r][p][c];
-                H0[c][2] = Lz[q][p][c];
-              }
-              nh_kin(H0, FiT, lnJ);
-              nh_apply(H, FiT, lnJ, lam, mu, S);
+              for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) FiT[i][j] = nw[qp & 1][3 * i + j];
+              nh_apply(H, FiT, nw[qp & 1][9], lam, mu, S);
             } else {
               T FiT[3][3], lnJ;
               if (!nh_kin(H, FiT, lnJ) && a.flags) atomicOr(a.flags, 1);

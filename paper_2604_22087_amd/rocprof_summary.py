@@ -7,11 +7,12 @@
   python -m paper_2604_22087_amd.rocprof_summary pmc DIR [--kernel SUBSTR]
       per-kernel mean / median / max of each counter from *counter_collection.csv
   python -m paper_2604_22087_amd.rocprof_summary traffic --fetch DIR --write DIR --cal-fetch DIR
-      --cal-write DIR --bench-json FILE --kernel SUBSTR --workload TEXT
+      --cal-write DIR --bench-json FILE --kernel SUBSTR --workload TEXT [--roofline KEY.PATH]
       HBM bytes per launch of one kernel from a FETCH_SIZE and a WRITE_SIZE run (KiB per dispatch),
       each scaled by what the same counter reads for a device copy of exactly 1 GiB each way
       (bench.py --copy-calib runs), next to the algorithmic bytes per launch of the benchmark line
-      in FILE, with the SHA-256 of the kernel sources the counters belong to (JSON)
+      in FILE (its "roofline" object, or the one at the dotted KEY.PATH), with the SHA-256 of the
+      kernel sources the counters belong to (JSON)
 """
 from __future__ import annotations
 
@@ -62,7 +63,7 @@ def _mean_counter(root, counter, kernel):
     return statistics.fmean(v), len(v)
 
 
-def traffic(fetch, write, cal_fetch, cal_write, bench_json, kernel, workload):
+def traffic(fetch, write, cal_fetch, cal_write, bench_json, kernel, workload, roofline="roofline"):
     import hashlib
     import json
     f_kib, nf = _mean_counter(fetch, "FETCH_SIZE", kernel)
@@ -72,7 +73,10 @@ def traffic(fetch, write, cal_fetch, cal_write, bench_json, kernel, workload):
     gib_kib = float(1 << 20)
     fs, ws = gib_kib / cf, gib_kib / cw
     line = [ln for ln in open(bench_json).read().splitlines() if ln.startswith("{")][-1]
-    algo = json.loads(line)["roofline"]["bytes_per_launch"]
+    node = json.loads(line)
+    for key in roofline.split("."):
+        node = node[key]
+    algo = node["bytes_per_launch"]
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
     h = hashlib.sha256()
     for f in ("fe_kernels.hip", "fe_internal.hpp", "fe_device.hpp"):
@@ -92,9 +96,10 @@ def main(argv=None):
     ap.add_argument("--kernel", default="")
     for opt in ("--fetch", "--write", "--cal-fetch", "--cal-write", "--bench-json", "--workload"):
         ap.add_argument(opt)
+    ap.add_argument("--roofline", default="roofline")
     a = ap.parse_args(argv)
     if a.mode == "traffic":
-        print(traffic(a.fetch, a.write, a.cal_fetch, a.cal_write, a.bench_json, a.kernel, a.workload))
+        print(traffic(a.fetch, a.write, a.cal_fetch, a.cal_write, a.bench_json, a.kernel, a.workload, a.roofline))
     else:
         print(trace(a.dir, a.min_ns, a.top) if a.mode == "trace" else pmc(a.dir, a.kernel))
 
