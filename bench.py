@@ -61,12 +61,12 @@ VALU_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 NH_APPLY_FLOPS_PER_ELEMENT = 396 + 8 * 160 + 396
 
 
-def measured_traffic():
-    """HBM bytes per launch of the fused CG operator from the committed rocprofv3 counter runs
+def measured_traffic(name="cg_operator_fiber64_f64_traffic.json"):
+    """HBM bytes per launch of a fused CG operator from the committed rocprofv3 counter runs
     (FETCH_SIZE / WRITE_SIZE, scaled by a 1 GiB copy), or None when the kernel source has
     changed since they were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "cg_operator_fiber64_f64_traffic.json")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -200,6 +200,7 @@ def neohooke_leg(n):
         t = ms / max(c, 1) * 1e-3
         flops = NH_APPLY_FLOPS_PER_ELEMENT * P.n_el
         peak = VALU_PEAK_TFLOPS[prec]
+        tr = measured_traffic("neohooke128_cg_operator_f64_traffic.json") if (n, prec) == (128, "f64") else None
         res[prec] = {"seconds": dt, "newton_iterations": info["newton_iterations"],
                      "pcg_iterations": info["pcg_iterations"], "ku_applies": info["operator_applies"],
                      "line_search_halvings": info["line_search_halvings"],
@@ -207,7 +208,8 @@ def neohooke_leg(n):
                      "ku_frac_hbm": by / max(c, 1) / t / 1e9 / HBM_PEAK_GBS,
                      "whole_ramp_gdofs": P.n_dof * info["operator_applies"] / dt / 1e9,
                      "roofline": {"bound": "hbm", "achieved": by / max(c, 1) / t / 1e9, "peak": HBM_PEAK_GBS,
-                                  "unit": "GB/s", "frac": by / max(c, 1) / t / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                                  "unit": "GB/s", "frac": by / max(c, 1) / t / 1e9 / HBM_PEAK_GBS,
+                                  "traffic": tr["traffic_bytes_per_launch"] if tr else None,
                                   "kernel": f"elem_kernel<{'float' if prec == 'f32' else 'double'}, OP_CG_APPLY, "
                                             f"MS_NH> (fused CG launch; F^-T and ln J of the linearisation read "
                                             f"per Gauss point as stored by the residual)",
