@@ -310,6 +310,20 @@ int fe_newton(fe_problem* p, const double* load_path_host, int n_steps, const fe
               void* u, void* state, double* sigma_bar_host, fe_newton_info* info_host,
               void* stream);
 
+/* Resume the load stepping of fe_newton at step first_step (0 <= first_step <= n_steps)
+ * of the same load_path_host, e.g. from a snapshot taken after step first_step - 1
+ * (the load-step history of Sec. II-A / V-A: converged field and committed plastic state).
+ * u: in, the converged field of step first_step - 1 (out: of the last step); state: in,
+ * the committed state after that step; u_prev: the converged field of step first_step - 2,
+ * read only by FE_PREDICT_EXTRAPOLATE when first_step >= 2 (required there, else may be
+ * NULL).  sigma_bar_host and opts->step_log_host keep the [n_steps] layout; rows before
+ * first_step are not written.  info counts the resumed steps only.  With the same inputs
+ * the steps run exactly the arithmetic of an uninterrupted fe_newton call (bit-identical
+ * results in deterministic mode). fe_newton(...) is fe_newton_resume with first_step = 0. */
+int fe_newton_resume(fe_problem* p, const double* load_path_host, int n_steps, int first_step,
+                     const fe_newton_opts* opts, void* u, const void* u_prev, void* state,
+                     double* sigma_bar_host, fe_newton_info* info_host, void* stream);
+
 /* Deterministic mode (on = 1) of a structured problem: the residual, the matrix-free operator
  * and the Jacobi diagonal (R(u), K x and diag K of Sec. II-A) sum element contributions in a
  * fixed order instead of with floating-point atomics -- each element writes its 24 nodal

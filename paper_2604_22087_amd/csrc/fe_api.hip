@@ -1118,10 +1118,15 @@ static int read_norm(fe_problem* p, const void* v, hipStream_t s, double* out) {
   return FE_OK;
 }
 
-extern "C" int fe_newton(fe_problem* p, const double* path, int n_steps, const fe_newton_opts* o, void* u,
-                         void* state, double* sigma_bar, fe_newton_info* info, void* stream) {
+// Load steps first_step .. n_steps-1 of path; u enters as the converged field of step
+// first_step - 1 (or the starting field), u_prev as that of step first_step - 2 (read only by
+// the extrapolating predictor when first_step >= 2).
+static int newton_run(fe_problem* p, const double* path, int n_steps, int first_step, const fe_newton_opts* o,
+                      void* u, const void* u_prev, void* state, double* sigma_bar, fe_newton_info* info,
+                      void* stream) {
   CHKP(p);
   if (!path || !o || !u || n_steps < 0) return arg_error("path, opts and u are required");
+  if (first_step < 0 || first_step > n_steps) return arg_error("first_step must be in [0, n_steps]");
   if (o->op != FE_OP_CSR && o->op != FE_OP_MATFREE) return arg_error("opts.op must be FE_OP_CSR or FE_OP_MATFREE");
   if (o->max_newton < 1 || !(o->newton_rtol >= 0) || !(o->pcg_rtol >= 0) || o->pcg_max_it < 1)
     return arg_error("invalid Newton options");
@@ -1136,6 +1141,8 @@ extern "C" int fe_newton(fe_problem* p, const double* path, int n_steps, const f
   if (!p->w_v2 && alloc(&p->w_v2, vec)) return FE_ERR_OOM;
   if (p->model_set == MS_J2 && !p->w_state && alloc(&p->w_state, rs * 7 * 8 * p->n_el)) return FE_ERR_OOM;
   const bool extrapolate = o->predictor == FE_PREDICT_EXTRAPOLATE && n_steps > 2;
+  if (extrapolate && first_step >= 2 && first_step < n_steps && !u_prev)
+    return arg_error("the extrapolating predictor resumed at step >= 2 needs u_prev");
   if (extrapolate && !p->w_uprev && alloc(&p->w_uprev, vec)) return FE_ERR_OOM;
   const bool use_csr = o->op == FE_OP_CSR || o->assemble_csr;
   if (use_csr) {
@@ -1179,11 +1186,12 @@ extern "C" int fe_newton(fe_problem* p, const double* path, int n_steps, const f
     }
     return std::sqrt(a);
   };
-  for (int step = 0; step < n_steps; ++step) {
+  for (int step = first_step; step < n_steps; ++step) {
     const fe_newton_info at_start = inf;
     if (extrapolate) {
       // w_uprev holds u_{k-2} from step 2 on; u += ratio (u - w_uprev), then w_uprev <- the old u
       if (step >= 2) {
+        if (step == first_step) HIPCHK(launch_axpby(p, p->n_dof, 1.0, u_prev, 0.0, p->w_uprev, s));
         const double d0 = frob_step(step - 1);
         const double ratio = d0 > 0 ? frob_step(step) / d0 : 0.0;
         HIPCHK(launch_axpby(p, p->n_dof, 1.0, u, 0.0, w, s));                // w = u_{k-1}
@@ -1268,6 +1276,17 @@ extern "C" int fe_newton(fe_problem* p, const double* path, int n_steps, const f
   HIPCHK(hipStreamSynchronize(s));
   if (info) *info = inf;
   return inf.status;
+}
+
+extern "C" int fe_newton(fe_problem* p, const double* path, int n_steps, const fe_newton_opts* o, void* u,
+                         void* state, double* sigma_bar, fe_newton_info* info, void* stream) {
+  return newton_run(p, path, n_steps, 0, o, u, nullptr, state, sigma_bar, info, stream);
+}
+
+extern "C" int fe_newton_resume(fe_problem* p, const double* path, int n_steps, int first_step,
+                                const fe_newton_opts* o, void* u, const void* u_prev, void* state,
+                                double* sigma_bar, fe_newton_info* info, void* stream) {
+  return newton_run(p, path, n_steps, first_step, o, u, u_prev, state, sigma_bar, info, stream);
 }
 
 extern "C" int fe_profile(fe_problem* p, int enable) {

@@ -240,12 +240,18 @@ __device__ __forceinline__ bool cg_stage_brick(const ElemArgs& a, int n, int a0,
       const int64_t dof = in[t] ? 3 * (gi + np1 * (gj + np1 * gk)) + c : 0;
       dofs[t] = dof;
       const int64_t b3 = dof - c;
+      if (blk) {  // the node's three components (slot k = component k)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const bool need = in[t] && (blk || k == c);
-        ro[t][k] = need ? RO[b3 + k] : T(0);
-        wo[t][k] = need && !first ? WO[b3 + k] : T(0);
-        so[t][k] = need && !first ? SO[b3 + k] : T(0);
+        for (int k = 0; k < 3; ++k) {
+          ro[t][k] = in[t] ? RO[b3 + k] : T(0);
+          wo[t][k] = in[t] && !first ? WO[b3 + k] : T(0);
+          so[t][k] = in[t] && !first ? SO[b3 + k] : T(0);
+        }
+      } else {  // the lane's own component only (slot 0): one coalesced load per vector
+        ro[t][0] = in[t] ? RO[dof] : T(0);
+        wo[t][0] = in[t] && !first ? WO[dof] : T(0);
+        so[t][0] = in[t] && !first ? SO[dof] : T(0);
+        ro[t][1] = ro[t][2] = wo[t][1] = wo[t][2] = so[t][1] = so[t][2] = T(0);
       }
       if (blk) {
         const T* mb = M + 2 * b3;  // 6 entries per node: xx, yy, zz, yz, xz, xy
@@ -277,17 +283,19 @@ __device__ __forceinline__ bool cg_stage_brick(const ElemArgs& a, int n, int a0,
       const bool fixed = in[t] && mkv != 0;
       T rn[3], sn[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
+      for (int k = 0; k < (blk ? 3 : 1); ++k) {
         sn[k] = wo[t][k] + beta * so[t][k];
         rn[k] = first ? ro[t][k] : ro[t][k] - alpha * sn[k];
       }
       T u, uo;
+      int cc = 0;  // slot of the lane's own component
       if (blk) {
         u = m[t][0] * rn[0] + m[t][1] * rn[1] + m[t][2] * rn[2];
         uo = m[t][0] * ro[t][0] + m[t][1] * ro[t][1] + m[t][2] * ro[t][2];
+        cc = c;
       } else {
-        u = m[t][0] * rn[c];
-        uo = m[t][0] * ro[t][c];
+        u = m[t][0] * rn[0];
+        uo = m[t][0] * ro[t][0];
       }
       if (own[t]) {
         const int64_t dof = dofs[t];
@@ -296,11 +304,11 @@ __device__ __forceinline__ bool cg_stage_brick(const ElemArgs& a, int n, int a0,
           const T pn = uo + beta * po[t];
           P[dof] = pn;
           X[dof] = xo[t] + alpha * pn;
-          SN[dof] = sn[c];
-          RN[dof] = rn[c];
+          SN[dof] = sn[cc];
+          RN[dof] = rn[cc];
         }
-        g += (double)rn[c] * (double)u;
-        rr += (double)rn[c] * (double)rn[c];
+        g += (double)rn[cc] * (double)u;
+        rr += (double)rn[cc] * (double)rn[cc];
       }
       if (fixed) {
         s_b[i] = u;

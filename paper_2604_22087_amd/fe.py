@@ -79,6 +79,8 @@ SIGNATURES = [
     ("fe_vjp", _i32, [_vp, _vp, _vp, _vp, _vp]),
     ("fe_newton", _i32, [_vp, ctypes.POINTER(_dbl), _i32, ctypes.POINTER(NewtonOpts), _vp, _vp,
                          ctypes.POINTER(_dbl), ctypes.POINTER(NewtonInfo), _vp]),
+    ("fe_newton_resume", _i32, [_vp, ctypes.POINTER(_dbl), _i32, _i32, ctypes.POINTER(NewtonOpts), _vp, _vp,
+                                _vp, ctypes.POINTER(_dbl), ctypes.POINTER(NewtonInfo), _vp]),
     ("fe_mean_stress", _i32, [_vp, _vp, _vp, ctypes.POINTER(_dbl), _vp]),
     ("fe_read_flags", _i32, [_vp, ctypes.POINTER(_i32), _vp]),
     ("fe_profile", _i32, [_vp, _i32]),
@@ -347,27 +349,37 @@ class Problem:
 
     def newton(self, load_path, u=None, state=None, op=OP_MATFREE, max_newton=20, newton_rtol=1e-8,
                pcg_rtol=1e-10, pcg_max_it=100000, assemble_csr=False, check=True, solver=SOLVER_CG, restart=0,
-               predictor=PREDICT_BOUNDARY):
+               predictor=PREDICT_BOUNDARY, first_step=0, u_prev=None):
         """Load stepping; load_path: sequence of 3x3 macro strains. Returns (u, state, sigma_bar, info);
-        info["steps"] lists (Newton iterations, line-search halvings, Krylov iterations) per load step."""
+        info["steps"] lists (Newton iterations, line-search halvings, Krylov iterations) per load step.
+        first_step > 0 resumes the same path at that step (fe_newton_resume): u and state are then
+        the converged field and committed state of step first_step - 1, u_prev the field of step
+        first_step - 2 (extrapolating predictor only); sigma_bar and info["steps"] cover the
+        resumed steps."""
         path = torch.as_tensor(np.asarray(load_path, dtype=np.float64)).reshape(-1, 9)
         k = path.shape[0]
         pa = (_dbl * (9 * k))(*path.reshape(-1).tolist())
         u = self.vector() if u is None else self._real(u, self.n_dof, "u")
         self._real(state, 56 * self.n_el, "state")
+        self._real(u_prev, self.n_dof, "u_prev")
         log = (_i32 * (3 * max(k, 1)))()
         opts = NewtonOpts(int(op), int(bool(assemble_csr)), int(max_newton), float(newton_rtol), float(pcg_rtol),
                           int(pcg_max_it), int(solver), int(restart), int(predictor),
                           ctypes.cast(log, ctypes.POINTER(_i32)))
         sig = (_dbl * (6 * max(k, 1)))()
         info = NewtonInfo()
-        st = self.lib.fe_newton(self.handle, pa, k, ctypes.byref(opts), _ptr(u), _ptr(state), sig,
-                                ctypes.byref(info), _stream())
+        if first_step:
+            st = self.lib.fe_newton_resume(self.handle, pa, k, int(first_step), ctypes.byref(opts), _ptr(u),
+                                           _ptr(u_prev), _ptr(state), sig, ctypes.byref(info), _stream())
+        else:
+            st = self.lib.fe_newton(self.handle, pa, k, ctypes.byref(opts), _ptr(u), _ptr(state), sig,
+                                    ctypes.byref(info), _stream())
         if check:
-            _check(st, "fe_newton")
-        sb = [list(sig[6 * i:6 * i + 6]) for i in range(k)]
+            _check(st, "fe_newton_resume" if first_step else "fe_newton")
+        f0 = int(first_step)
+        sb = [list(sig[6 * i:6 * i + 6]) for i in range(f0, k)]
         out = {f: getattr(info, f) for f, _ in NewtonInfo._fields_}
-        out["steps"] = [tuple(log[3 * i:3 * i + 3]) for i in range(info.steps_done)]
+        out["steps"] = [tuple(log[3 * i:3 * i + 3]) for i in range(f0, f0 + info.steps_done)]
         return u, state, sb, out
 
     def mean_stress(self, u, state_in=None):
