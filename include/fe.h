@@ -146,7 +146,8 @@ int fe_problem_create_hex8(fe_problem** out, int64_t n_nodes, int64_t n_el, cons
 void fe_problem_destroy(fe_problem* p);
 
 /* Sizes: out_host[0..5] = n (0 for a general mesh), n_el, n_nodes, n_dof,
- * n_qp (= 8 n_el), nnz. */
+ * n_qp (= 8 n_el), nnz.
+ * Sizes of the discretisation of Sec. II-A and of its sparse matrix (Sec. III-B). */
 int fe_problem_sizes(const fe_problem* p, int64_t* out_host);
 
 /* Materials (the phase-dependent laws of Sec. V-A).  phase: uint8 [n_el] with
@@ -189,15 +190,18 @@ int fe_csr_indices(fe_problem* p, int32_t* row_ptr, int32_t* col_idx, void* stre
 
 /* Jacobian values K(u) in the pattern of fe_csr_indices: vals real [nnz],
  * duplicates summed.  Linearises at (u, state_in) first (as FE_STORE_TANGENT).
- * apply_bc = 1 zeroes constrained rows and columns and puts 1 on their diagonal. */
+ * apply_bc = 1 zeroes constrained rows and columns and puts 1 on their diagonal.
+ * The Jacobian of Sec. II-A as the sparse matrix of Sec. III-B. */
 int fe_tangent_csr(fe_problem* p, const void* u, const void* state_in, void* vals, int apply_bc,
                    void* stream);
 
 /* Matrix-free y = K x at the stored linearisation (the elastic K when the
- * problem has only linear phases).  apply_bc = 1 gives P_f K P_f x + P_b x. */
+ * problem has only linear phases).  apply_bc = 1 gives P_f K P_f x + P_b x.
+ * The matrix-free operator of Sec. III-A. */
 int fe_apply_matfree(fe_problem* p, const void* x, void* y, int apply_bc, void* stream);
 
-/* CSR y = A x for any CSR matrix with n_dof rows (row_ptr, col_idx int32). */
+/* CSR y = A x for any CSR matrix with n_dof rows (row_ptr, col_idx int32).
+ * The explicit-matrix mat-vec timed in Fig. 3. */
 int fe_apply_csr(fe_problem* p, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
                  const void* x, void* y, void* stream);
 
@@ -205,7 +209,8 @@ int fe_apply_csr(fe_problem* p, const int32_t* row_ptr, const int32_t* col_idx, 
  * (rows 3a, 3a+1, 3a+2 have identical column lists): the column indices and the
  * gathered x of a node's first row serve all three rows, so index traffic is a
  * third of fe_apply_csr's.  Results equal fe_apply_csr's (same products and sums,
- * possibly in another order).  The pattern is not checked. */
+ * possibly in another order).  The pattern is not checked.
+ * The explicit-matrix mat-vec of Fig. 3 for this pattern. */
 int fe_apply_csr_nodal(fe_problem* p, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
                        const void* x, void* y, void* stream);
 
@@ -239,7 +244,8 @@ int fe_set_preconditioner(fe_problem* p, int kind);
 /* z = M^-1 r for the preconditioner chosen by fe_set_preconditioner, set up as the
  * solvers set it up: from the CSR matrix when row_ptr, col_idx and vals are given
  * (already eliminated; required for FE_PC_ILU0), else from the stored
- * linearisation (FE_ERR_STATE without one).  r, z: real [n_dof], distinct. */
+ * linearisation (FE_ERR_STATE without one).  r, z: real [n_dof], distinct.
+ * Preconditioners of the Krylov solves compared in Sec. V-B (Fig. 7). */
 int fe_apply_preconditioner(fe_problem* p, const int32_t* row_ptr, const int32_t* col_idx,
                             const void* vals, const void* r, void* z, void* stream);
 
@@ -279,7 +285,8 @@ int fe_gmres(fe_problem* p, int op, const int32_t* row_ptr, const int32_t* col_i
 
 /* Vector-Jacobian product with respect to the per-element modulus scale s_e:
  * out[e] = lambda_e^T d r_e / d s_e, real [n_el].  Supported for linear and
- * Neo-Hookean phases (r_e is proportional to s_e); FE_ERR_ARG with J2 phases. */
+ * Neo-Hookean phases (r_e is proportional to s_e); FE_ERR_ARG with J2 phases.
+ * Adjoint gradients for the differentiable-simulation use of Sec. I. */
 int fe_vjp(fe_problem* p, const void* u, const void* lambda, void* out, void* stream);
 
 /* One backward step of the discrete adjoint through a J2 load path (history
@@ -305,7 +312,8 @@ int fe_vjp_path(fe_problem* p, const void* u, const void* state_in, const void* 
  * while ||P_f R(u + s w)|| >= ||P_f R(u)||.
  * u: real [n_dof] in/out (the starting field); state: real [7][8][n_el] in/out
  * (NULL for problems without J2 phases); sigma_bar_host: [n_steps][6] volume
- * averaged stress after each step, or NULL. */
+ * averaged stress after each step, or NULL.
+ * Newton's method for R(u) = 0 (Sec. II-A) over the load ramps of Sec. V-A. */
 int fe_newton(fe_problem* p, const double* load_path_host, int n_steps, const fe_newton_opts* opts,
               void* u, void* state, double* sigma_bar_host, fe_newton_info* info_host,
               void* stream);
@@ -355,7 +363,8 @@ int fe_set_fp32_accumulation(fe_problem* p, int on);
 int fe_commit_state(fe_problem* p, const void* state_trial, void* state, void* stream);
 
 /* Volume-averaged stress (1/V) sum_q w_q detJ_q sigma_q at (u, state_in),
- * written to sigma_host[6] in Voigt order [xx,yy,zz,yz,xz,xy]. */
+ * written to sigma_host[6] in Voigt order [xx,yy,zz,yz,xz,xy].
+ * The homogenised (effective) response of the RVE, Sec. V-A. */
 int fe_mean_stress(fe_problem* p, const void* u, const void* state_in, double* sigma_host,
                    void* stream);
 
@@ -374,18 +383,21 @@ int fe_mean_stress(fe_problem* p, const void* u, const void* state_in, double* s
  * and 4 (compulsory traffic: x read and y written once, phase ids, the stored
  * tangent values the kernel must read at the current linearisation; CSR:
  * values, column indices (one list per node for class 4), row pointers, x and
- * y once), 0 for classes 2 and 3; then clears the records.  out_host: 15 doubles. */
+ * y once), 0 for classes 2 and 3; then clears the records.  out_host: 15 doubles.
+ * Per-operation timing as in the measurements of Sec. V-B. */
 int fe_profile(fe_problem* p, int enable);
 int fe_profile_read(fe_problem* p, double* out_host);
 
 /* Statistics of the stored linearisation: out_host[0] = Gauss points of J2
- * phases, out_host[1] = those that were plastic (synchronises). */
+ * phases, out_host[1] = those that were plastic (synchronises).
+ * Of the J2 phase's constitutive update (Sec. V-A). */
 int fe_linearization_stats(fe_problem* p, int64_t* out_host, void* stream);
 
 /* Device-side error flags raised by element kernels since the last read
  * (bit 0: inverted element; bit 1: a node block of the block-Jacobi
  * preconditioner with determinant <= 0; bit 2: a singular ILU(0) pivot block).
- * Synchronises and clears. */
+ * Synchronises and clears.
+ * Failures of the element computations of Sec. II-A. */
 int fe_read_flags(fe_problem* p, int* flags_host, void* stream);
 
 /* ---- learned constitutive surrogate (Sec. III-B: a surrogate may replace the
@@ -399,12 +411,14 @@ enum { FE_MLP_IN = 13, FE_MLP_HIDDEN = 128, FE_MLP_OUT = 6, FE_MLP_PARAMS = 3559
 /* y = net(x): x float [n][13], y float [n][6].  jac (float [n][6][6], may be
  * NULL): jac[s][o][j] = dy_o/dx_j for the first six inputs (forward-mode
  * tangents carried through FP32 matrix cores).  cache (float [n][3][128], may
- * be NULL): hidden pre-activations, for fe_mlp_backward. */
+ * be NULL): hidden pre-activations, for fe_mlp_backward.
+ * Learned constitutive surrogate (the surrogate-model remark of Sec. III-B). */
 int fe_mlp_forward(const float* W, const float* x, float* y, float* jac, float* cache, int64_t n, void* stream);
 
 /* Gradients of L = mean_s sum_o (y - target)^2 over the n samples of one batch:
  * dW (float [FE_MLP_PARAMS]) is overwritten; loss_dev (double [1]) receives L;
- * work is scratch of float [n][3*128+6] (per-sample pre-activation gradients). */
+ * work is scratch of float [n][3*128+6] (per-sample pre-activation gradients).
+ * Training of the learned surrogate of Sec. III-B. */
 int fe_mlp_backward(const float* W, const float* x, const float* cache, const float* y, const float* target,
                     float* dW, double* loss_dev, float* work, int64_t n, void* stream);
 
@@ -419,7 +433,8 @@ int fe_mlp_backward(const float* W, const float* x, const float* cache, const fl
 int fe_mlp_backward_static(const float* W, const float* x, const float* cache, const float* y, const float* target,
                            float* dW, double* loss_dev, int64_t n, void* stream);
 
-/* One Adam step (Kingma & Ba), t >= 1: m, v are the first/second moment buffers. */
+/* One Adam step (Kingma & Ba), t >= 1: m, v are the first/second moment buffers.
+ * Training of the learned surrogate of Sec. III-B. */
 int fe_adam_step(float* W, const float* dW, float* m, float* v, int64_t n_param, double lr, double beta1,
                  double beta2, double eps, int t, void* stream);
 
@@ -436,17 +451,20 @@ int fe_adam_step(float* W, const float* dW, float* m, float* v, int64_t n_param,
  * network Jacobian (the linear solver is CG).  W (float [FE_MLP_PARAMS],
  * device) is borrowed until the next call; NULL switches the surrogate off.
  * Every fe_residual then runs three launches (list plastic-trial points,
- * network, residual) and synchronises once. */
+ * network, residual) and synchronises once.
+ * The learned surrogate of Sec. III-B in place of the return map. */
 int fe_set_surrogate(fe_problem* p, const float* W, double fallback_tol);
 
 /* Tangent handed to the linear solver at accepted surrogate points: 0 (default)
  * the symmetric part of the network Jacobian (for CG), 1 the Jacobian itself,
  * which makes the operator nonsymmetric (solve with FE_SOLVER_BICGSTAB /
- * fe_bicgstab).  Takes effect at the next residual evaluation. */
+ * fe_bicgstab).  Takes effect at the next residual evaluation.
+ * Linearisation of the learned surrogate of Sec. III-B. */
 int fe_set_surrogate_tangent(fe_problem* p, int full);
 
 /* After fe_residual with a surrogate: out_host = {points given to the network,
- * accepted, fallbacks} (synchronises). */
+ * accepted, fallbacks} (synchronises).
+ * Of the learned surrogate of Sec. III-B. */
 int fe_surrogate_stats(fe_problem* p, int64_t* out_host, void* stream);
 
 /* Training-sample capture: while set (x != NULL), every fe_residual appends,
@@ -454,7 +472,8 @@ int fe_surrogate_stats(fe_problem* p, int64_t* out_host, void* stream);
  * passes a 1-in-stride thinning, the normalised network input x [13] and the
  * exact return-map stress y [6] (same normalisation as fe_set_surrogate) to the
  * caller's buffers (float [capacity][13], [capacity][6]) at slot *count_dev
- * (device unsigned, incremented; slots beyond capacity are dropped). */
+ * (device unsigned, incremented; slots beyond capacity are dropped).
+ * Training data of the learned surrogate of Sec. III-B. */
 int fe_set_capture(fe_problem* p, float* x, float* y, int64_t capacity, unsigned int* count_dev, int stride);
 
 const char* fe_status_string(int status);
