@@ -71,7 +71,8 @@ def capture_samples(problems_and_paths, capacity, stride=1):
         P.set_capture(x, y, count, stride=st if st else stride)
         P.newton(path, state=P.state(), op=fe.OP_MATFREE, newton_rtol=1e-8, pcg_rtol=1e-10, max_newton=30)
         P.set_capture(None)
-    m = min(int(count.item()), capacity)
+    capture_samples.last_count = int(count.item())  # points offered, including those past capacity
+    m = min(capture_samples.last_count, capacity)
     return x[:m].contiguous(), y[:m].contiguous()
 
 
@@ -120,13 +121,21 @@ def relative_stress_error(W, x, y):
 DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "surrogate_j2.npy")
 
 
-def training_set(capacity=6_000_000):
-    """Return-map samples of the config-2 matrix material: 32^3 fiber RVE uniaxial and shear
-    ramps to 0.03 (every plastic-trial point of every Newton iterate), 64^3 uniaxial ramp to
-    0.02 (hashed 1-in-2 thinning)."""
+def training_set(capacity=10_000_000):
+    """Return-map samples of the fiber-RVE matrix material from the plastic-trial points of every
+    Newton iterate of four ramps (32^3 uniaxial and shear to 0.03, 64^3 uniaxial and shear to
+    0.02), thinned by one common hashed stride so that every ramp contributes in proportion:
+    a counting pass gives the number of points offered, the stride is chosen for ~95 % of
+    `capacity`, and the second pass captures."""
     p32, p64 = fiber_problem(32), fiber_problem(64)
-    return capture_samples([(p32, ramp(0.03, 10), 1), (p32, ramp(0.03, 10, shear=True), 1),
-                            (p64, ramp(0.02, 10), 2)], capacity)
+    ramps = [(p32, ramp(0.03, 10)), (p32, ramp(0.03, 10, shear=True)), (p64, ramp(0.02, 10)),
+             (p64, ramp(0.02, 10, shear=True))]
+    capture_samples([(P, path, 1) for P, path in ramps], 1)
+    offered = capture_samples.last_count
+    stride = max(1, math.ceil(offered / (0.95 * capacity)))
+    x, y = capture_samples([(P, path, stride) for P, path in ramps], capacity)
+    training_set.offered, training_set.stride = offered, stride
+    return x, y
 
 
 def load_weights(path=DEFAULT_WEIGHTS):
@@ -143,7 +152,7 @@ def main(argv=None):
     import time
     ap = argparse.ArgumentParser(description=main.__doc__)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
-    ap.add_argument("--samples", type=int, default=6_000_000)
+    ap.add_argument("--samples", type=int, default=10_000_000)
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--batch", type=int, default=4096)
@@ -157,7 +166,8 @@ def main(argv=None):
     err = relative_stress_error(W, x[:200000], y[:200000]).cpu().numpy()
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out, W.cpu().numpy())
-    meta = dict(samples=int(x.shape[0]), epochs=args.epochs, lr=args.lr, batch=args.batch, seed=5,
+    meta = dict(samples=int(x.shape[0]), samples_offered=training_set.offered, stride=training_set.stride,
+                captured=capture_samples.last_count, epochs=args.epochs, lr=args.lr, batch=args.batch, seed=5,
                 capture_seconds=t1 - t0, train_seconds=t2 - t1, final_train_loss=hist[-1]["train_loss"],
                 final_val_loss=hist[-1]["val_loss"], rel_stress_err_median=float(np.median(err)),
                 rel_stress_err_p99=float(np.percentile(err, 99)))
