@@ -1174,8 +1174,23 @@ __global__ __launch_bounds__(256) void tangent_rows_kernel(TanArgs a, T* vals, i
   const int tid = threadIdx.x;
   const T inv_h = T(1.0 / a.h), w = T(0.125 * a.h * a.h * a.h);
 
-  // phase 1: elements (i0 - 1 .. i0 + TR_NODES - 1) x (j - 1, j) x (k - 1, k), all 8 points
+  // phase 1: elements (i0 - 1 .. i0 + TR_NODES - 1) x (j - 1, j) x (k - 1, k), all 8 points.
+  // Every load of the phase is issued before any of them is used: the constrained-dof flags of
+  // the tile's nodes, and per set the phase id, modulus scale and the six stored-tangent words
+  // (read for every element: the words exist for all of them and are used at J2 points only)
   static_assert(TR_SETS <= 256, "one coefficient set per lane");
+  uint8_t mk_v = 0;
+  const bool mk_lane = tid < 27 * (TR_NODES + 2);
+  int mk_c = 0, mk_x = 0, mk_y = 0, mk_z = 0;
+  if (mk_lane) {  // nodes (i0 - 1 .. i0 + TR_NODES) x (j - 1 .. j + 1) x (k - 1 .. k + 1)
+    mk_c = tid % 3;
+    mk_x = (tid / 3) % (TR_NODES + 2);
+    mk_y = (tid / (3 * (TR_NODES + 2))) % 3;
+    mk_z = tid / (9 * (TR_NODES + 2));
+    const int gx = i0 - 1 + mk_x, gy = j - 1 + mk_y, gz = k - 1 + mk_z;
+    const bool in = apply_bc && a.mask && gx >= 0 && gx <= n && gy >= 0 && gy <= n && gz >= 0 && gz <= n;
+    mk_v = in ? a.mask[3 * (gx + np1 * (gy + np1 * (int64_t)gz)) + mk_c] : (uint8_t)0;
+  }
   {
     const int si = tid;
     const int qp = si & 7, el = si >> 3;
@@ -1185,15 +1200,19 @@ __global__ __launch_bounds__(256) void tangent_rows_kernel(TanArgs a, T* vals, i
     int sur = -1;
     if (si < TR_SETS && ea >= 0 && ea < n && eb >= 0 && eb < n && ec >= 0 && ec < n) {
       const int64_t e = ea + (int64_t)n * (eb + (int64_t)n * ec);
-      const PhaseConst pc = a.mat.ph[a.phase[e]];
+      const int ph = a.phase[e];
       const T sc = a.scale ? static_cast<const T*>(a.scale)[e] : T(1);
+      T tn[6];
+      if (MS == MS_J2) {
+        const T* tg = static_cast<const T*>(a.tangent);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) tn[q] = tg[(int64_t)(q * 8 + qp) * ne + e];
+      }
+      const PhaseConst pc = a.mat.ph[ph];
       co[0] = T(pc.lam) * sc;
       co[1] = T(pc.mu) * sc;
       if (MS == MS_J2 && pc.model == FE_J2) {
-        const T* tg = static_cast<const T*>(a.tangent);
-        T tn[6], N[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) tn[q] = tg[(int64_t)(q * 8 + qp) * ne + e];
+        T N[6];
         if (tn[0] < T(-1.5)) {
           sur = a.sur_map[(int64_t)qp * ne + e];
         } else {
@@ -1215,13 +1234,7 @@ __global__ __launch_bounds__(256) void tangent_rows_kernel(TanArgs a, T* vals, i
       if ((si & 7) == 0) s_uni[si >> 3] = ((bal >> (tid & 63 & ~7)) & 0xffull) == 0xffull ? 1 : 0;
     }
   }
-  if (tid < 27 * (TR_NODES + 2)) {  // nodes (i0 - 1 .. i0 + TR_NODES) x (j - 1 .. j + 1) x (k - 1 .. k + 1)
-    const int c = tid % 3, xl = (tid / 3) % (TR_NODES + 2), yl = (tid / (3 * (TR_NODES + 2))) % 3,
-              zl = tid / (9 * (TR_NODES + 2));
-    const int gx = i0 - 1 + xl, gy = j - 1 + yl, gz = k - 1 + zl;
-    const bool in = apply_bc && a.mask && gx >= 0 && gx <= n && gy >= 0 && gy <= n && gz >= 0 && gz <= n;
-    s_mk[zl][yl][xl][c] = in ? a.mask[3 * (gx + np1 * (gy + np1 * (int64_t)gz)) + c] : (uint8_t)0;
-  }
+  if (mk_lane) s_mk[mk_z][mk_y][mk_x][mk_c] = mk_v;
   __syncthreads();
 
   // phase 2: one task per lane
