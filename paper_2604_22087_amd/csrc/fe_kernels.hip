@@ -1403,6 +1403,26 @@ hipError_t launch_tangent_csr(const fe_problem* p, void* vals, int apply_bc, hip
 // CSR sparse mat-vec: LPR lanes per row, contiguous row segments (coalesced),
 // butterfly reduction inside the lane group.
 
+// One lane's share of a CSR row dot product: entries b + lane, b + lane + LPR, ... < e, two
+// column steps per batch with both index loads, gathers and values issued before the
+// multiply-adds (the gather depends on its index load; one step at a time serialises the two),
+// summed in entry order.
+template <typename T, int LPR>
+__device__ __forceinline__ T csr_row_dot(const int32_t* __restrict__ ci, const T* __restrict__ v,
+                                         const T* __restrict__ x, int b, int e, int lane) {
+  T acc = 0;
+  int k = b + lane;
+  for (; k + LPR < e; k += 2 * LPR) {
+    const int c0 = ci[k], c1 = ci[k + LPR];
+    const T v0 = v[k], v1 = v[k + LPR];
+    const T x0 = x[c0], x1 = x[c1];
+    acc += v0 * x0;
+    acc += v1 * x1;
+  }
+  if (k < e) acc += v[k] * x[ci[k]];
+  return acc;
+}
+
 template <typename T, int LPR>
 __global__ __launch_bounds__(256) void spmv_kernel(int64_t n_rows, const int32_t* __restrict__ rp,
                                                    const int32_t* __restrict__ ci, const T* __restrict__ v,
@@ -1411,10 +1431,7 @@ __global__ __launch_bounds__(256) void spmv_kernel(int64_t n_rows, const int32_t
   const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
   const int lane = threadIdx.x % LPR;
   T acc = 0;
-  if (row < n_rows) {
-    const int b = rp[row], e = rp[row + 1];
-    for (int k = b + lane; k < e; k += LPR) acc += v[k] * x[ci[k]];
-  }
+  if (row < n_rows) acc = csr_row_dot<T, LPR>(ci, v, x, rp[row], rp[row + 1], lane);
 #pragma unroll
   for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
   if (row < n_rows && lane == 0) y[row] = acc;
@@ -1987,10 +2004,7 @@ __global__ __launch_bounds__(256) void cg_spmv_kernel(int64_t n_rows, const int3
   for (int64_t row0 = (int64_t)blockIdx.x * RPB; row0 < n_rows; row0 += (int64_t)gridDim.x * RPB) {
     const int64_t row = row0 + threadIdx.x / LPR;
     T acc = 0;
-    if (row < n_rows) {
-      const int b = rp[row], e = rp[row + 1];
-      for (int k = b + lane; k < e; k += LPR) acc += v[k] * p[ci[k]];
-    }
+    if (row < n_rows) acc = csr_row_dot<T, LPR>(ci, v, p, rp[row], rp[row + 1], lane);
 #pragma unroll
     for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
     if (row < n_rows && lane == 0) {
