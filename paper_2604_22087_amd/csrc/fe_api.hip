@@ -127,7 +127,6 @@ void fe_problem_destroy(fe_problem* p) {
   free_dev(p->scale);
   free_dev(p->mask);
   free_dev(p->tangent);
-  free_dev(p->u_lin);
   free_dev(p->w_r);
   free_dev(p->w_p);
   free_dev(p->w_q);
@@ -399,10 +398,6 @@ int fe_set_materials(fe_problem* p, const uint8_t* phase, int n_phases, const in
     int st = alloc(&p->tangent, rs * comps * 8 * p->n_el);
     if (st) return st;
   }
-  if (nh && !p->u_lin) {
-    int st = alloc(&p->u_lin, rs * p->n_dof);
-    if (st) return st;
-  }
   p->mat = m;
   p->model_set = j2 ? MS_J2 : (nh ? MS_NH : MS_LINEAR);
   p->materials_set = true;
@@ -450,7 +445,6 @@ static ElemArgs base_args(const fe_problem* p) {
 
 static int residual_impl(fe_problem* p, const void* u, const void* state_in, void* state_out, void* r, int flags,
                          double* stress_sum, hipStream_t s) {
-  const size_t rs = real_size(p);
   if (r) HIPCHK(launch_fill(p, r, p->n_dof, 0.0, s));
   ElemArgs a = base_args(p);
   a.x = u;
@@ -509,10 +503,7 @@ static int residual_impl(fe_problem* p, const void* u, const void* state_in, voi
     a.sur_salt = p->cap_salt++ * 0x9E3779B9u;
   }
   PROF(p, s, 2, launch_elem(p, OP_RESID, a, s));
-  if (a.store_tangent) {
-    if (p->model_set == MS_NH) HIPCHK(hipMemcpyAsync(p->u_lin, u, rs * p->n_dof, hipMemcpyDeviceToDevice, s));
-    p->lin_valid = true;
-  }
+  if (a.store_tangent) p->lin_valid = true;
   return FE_OK;
 }
 
@@ -614,7 +605,6 @@ int fe_apply_matfree(fe_problem* p, const void* x, void* y, int apply_bc, void* 
   HIPCHK(launch_fill(p, y, p->n_dof, 0.0, S(stream)));
   ElemArgs a = base_args(p);
   a.x = x;
-  a.xlin = p->u_lin;
   a.y = y;
   a.apply_bc = apply_bc ? 1 : 0;
   PROF(p, S(stream), 0, launch_elem(p, OP_APPLY, a, S(stream)));
@@ -726,7 +716,6 @@ static int ipcg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci,
     if (op == FE_OP_CSR) return launch_spmv_stop(p, rp, ci, vals, pv, q, stop, s);
     ElemArgs a = base_args(p);
     a.x = pv;
-    a.xlin = p->u_lin;
     a.y = q;
     a.apply_bc = 1;
     return launch_elem_stop(p, OP_APPLY, a, stop, s);
@@ -873,7 +862,6 @@ static int bicg_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci,
     if (op == FE_OP_CSR) return launch_spmv_stop(p, rp, ci, vals, in, out, stop, s);
     ElemArgs a = base_args(p);
     a.x = in;
-    a.xlin = p->u_lin;
     a.y = out;
     a.apply_bc = 1;
     return launch_elem_stop(p, OP_APPLY, a, stop, s);
@@ -947,7 +935,6 @@ static int gmres_run(fe_problem* p, int op, const int32_t* rp, const int32_t* ci
     if (op == FE_OP_CSR) return launch_spmv_stop(p, rp, ci, vals, in, out, stp, s);
     ElemArgs a = base_args(p);
     a.x = in;
-    a.xlin = p->u_lin;
     a.y = out;
     a.apply_bc = 1;
     return launch_elem_stop(p, OP_APPLY, a, stp, s);
@@ -1337,8 +1324,7 @@ static int operator_bytes(fe_problem* p, int op, hipStream_t s, double* bytes) {
   double b = 2.0 * w * (double)p->n_dof + (double)p->n_el + w * ((double)st[0] + 5.0 * (double)st[1]);
   if (p->general)  // connectivity and coordinates; all six tangent words of every J2 point
     b = 2.0 * w * (double)p->n_dof + 33.0 * (double)p->n_el + 3.0 * w * (double)p->n_nodes + 6.0 * w * (double)st[0];
-  if (p->model_set == MS_NH)  // general meshes gather the linearisation point; the cube reads the
-    b += p->general ? w * (double)p->n_dof : 80.0 * w * (double)p->n_nh_el;  // stored F^-T, ln J per point
+  if (p->model_set == MS_NH) b += 80.0 * w * (double)p->n_nh_el;  // stored F^-T and ln J of every point
   if (p->scale) b += w * (double)p->n_el;  // per-element modulus scale
   *bytes = b;
   return FE_OK;

@@ -160,7 +160,7 @@ static GenArgs gen_args(const fe_problem* p) {
 template <typename T, int OP, int MS>
 __global__ __launch_bounds__(GBLOCK) void gen_elem_kernel(GenArgs g, ElemArgs a, const int* stop) {
   constexpr bool APPLY = OP == OP_APPLY;
-  constexpr bool NEED_L = (OP == OP_VJP) || (APPLY && MS == MS_NH);
+  constexpr bool NEED_L = OP == OP_VJP;
   __shared__ T s_c[GEL][8][3];
   __shared__ T s_x[GEL][8][3];
   __shared__ T s_l[NEED_L ? GEL : 1][8][3];
@@ -235,11 +235,13 @@ __global__ __launch_bounds__(GBLOCK) void gen_elem_kernel(GenArgs g, ElemArgs a,
       }
     }
     if (MS == MS_NH && pc.model == FE_NEOHOOKE) {
-      if (APPLY) {
-        T H0[3][3], FiT[3][3], lnJ;
-        field_grad<T>(s_l[NEED_L ? el : 0], gr, H0);
-        nh_kin(H0, FiT, lnJ);
-        nh_apply(H, FiT, lnJ, lam, mu, S);
+      if (APPLY) {  // F^-T and ln J of the linearisation, as the residual stored them
+        T FiT[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) FiT[i][j] = tang[(int64_t)(3 * i + j) * 8 * ne + pidx];
+        nh_apply(H, FiT, tang[(int64_t)9 * 8 * ne + pidx], lam, mu, S);
       } else {
         T FiT[3][3], lnJ;
         if (!nh_kin(H, FiT, lnJ) && a.flags) atomicOr(a.flags, 1);
@@ -982,7 +984,6 @@ hipError_t gen_cg_operator(const fe_problem* p, hipStream_t s) {
   a.flags = p->flags;
   a.mat = p->mat;
   a.x = p->w_p;
-  a.xlin = p->u_lin;
   a.y = p->w_q;
   a.apply_bc = 1;
   const int* stop = &p->ctrl->status;

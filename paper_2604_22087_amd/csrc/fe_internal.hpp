@@ -126,7 +126,7 @@ struct ElemArgs {
   const void* scale;      // real [n_el] or null
   const uint8_t* mask;    // [n_dof] or null
   const void* x;          // gathered field (u for RESID/VJP, x for APPLY)
-  const void* xlin;       // Neo-Hookean linearisation point (APPLY) / lambda (VJP)
+  const void* xlin;       // lambda (VJP)
   void* y;                // scattered output (may be null for RESID = linearise only)
   const void* state_in;   // J2 state [7][8][n_el] or null
   void* state_out;        // J2 trial state or null
@@ -191,7 +191,6 @@ struct fe_problem {
   void* scale = nullptr;      // real [n_el] or null
   uint8_t* mask = nullptr;    // [n_dof] or null
   void* tangent = nullptr;    // J2 compact tangent [6][8][n_el]
-  void* u_lin = nullptr;      // Neo-Hookean linearisation point [n_dof]
   bool lin_valid = false;
   // solver workspace
   void* w_r = nullptr;

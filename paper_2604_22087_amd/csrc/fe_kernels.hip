@@ -2093,7 +2093,6 @@ static hipError_t cg_operator_t(const fe_problem* p, int op, const int32_t* rp, 
     a.sur_map = p->sur_map;
     a.sur_D = p->sur_D;
     a.x = p->w_p;
-    a.xlin = p->u_lin;
     a.y = p->w_q;
     a.apply_bc = 1;
     a.elf = p->w_elf;
@@ -2165,7 +2164,6 @@ template <typename T> static hipError_t cgs_operator_t(const fe_problem* p, T* x
   a.phase = p->phase;
   a.scale = p->scale;
   a.mask = p->mask;
-  a.xlin = p->u_lin;
   a.tangent = p->tangent;
   a.apply_bc = 1;
   a.mat = p->mat;
