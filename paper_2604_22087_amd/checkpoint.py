@@ -78,7 +78,8 @@ def newton_checkpointed(P, load_path, file, u=None, state=None, every=1, resume=
     if resume and os.path.exists(file):
         snap = load_snapshot(file, P)
         stored = np.asarray(snap["load_path"], dtype=np.float64).reshape(-1, 9)
-        if stored.shape[0] > K or not np.array_equal(stored[:snap["step"] + 1], path[:snap["step"] + 1]):
+        done = snap["step"] + 1
+        if done > K or not np.array_equal(stored[:done], path[:done]):
             raise ValueError(f"{file}: snapshot of a different load path")
         u.copy_(snap["u"])
         if state is not None:

@@ -47,3 +47,15 @@ def test_snapshot_of_another_problem_is_rejected(tmp_path):
     save_file({"u": torch.zeros(3)}, other, metadata={"snapshot": '{"format": "something else"}'})
     with pytest.raises(ValueError):
         checkpoint.load_snapshot(other, _fake(3, 1))
+
+
+def test_resume_rejects_a_different_path(tmp_path):
+    f = str(tmp_path / "s.safetensors")
+    P = _fake(81, 8)
+    path = [np.diag([0.001 * k, 0, 0]) for k in range(1, 4)]
+    checkpoint.save_snapshot(f, P, 1, path, torch.zeros(81, dtype=torch.float64))
+    other = [np.diag([0.002 * k, 0, 0]) for k in range(1, 4)]
+    with pytest.raises(ValueError):
+        checkpoint.newton_checkpointed(P, other, f, u=torch.zeros(81, dtype=torch.float64))
+    with pytest.raises(ValueError):  # the path ends before the snapshot's step
+        checkpoint.newton_checkpointed(P, path[:1], f, u=torch.zeros(81, dtype=torch.float64))
