@@ -1085,71 +1085,10 @@ hipError_t launch_csr_pattern(const fe_problem* p, int32_t* row_ptr, int32_t* co
   return hipGetLastError();
 }
 
-// CSR values: one lane per (row node P, neighbour Q) 3x3 block, summed over the
-// elements that contain both nodes and their Gauss points (no atomics, deterministic).
-// Lane mapping: a workgroup takes TAN_NODES consecutive nodes and all 27 neighbour slots of
-// each, slot-major, with the slots ordered by how many elements the node pair shares (8 for
-// the node itself, then 4, 2, 1): the four waves hold the node itself and its 6 face
-// neighbours, 7 edge neighbours, 5 edge and 2 corner neighbours, 6 corner neighbours, so a
-// wave's lanes run (nearly) the same number of element iterations and read the stored
-// tangents of consecutive elements; the workgroup writes whole CSR row segments.
-constexpr int TAN_NODES = 9;
-constexpr int TAN_BLOCK = 256;  // 27 * TAN_NODES = 243 lanes used
-__constant__ int tan_slot_order[27] = {13, 4, 10, 12, 14, 16, 22,                        // self, faces
-                                       1, 3, 5, 7, 9, 11, 15, 17, 19, 21, 23, 25,       // edges
-                                       0, 2, 6, 8, 18, 20, 24, 26};                     // corners
-
-template <typename T, int MS>
-__global__ __launch_bounds__(TAN_BLOCK) void tangent_csr_kernel(TanArgs a, T* vals, int apply_bc) {
-  const int n = a.n;
-  const int64_t np1 = n + 1;
-  if (threadIdx.x >= 27 * TAN_NODES) return;
-  const int64_t P = (int64_t)blockIdx.x * TAN_NODES + threadIdx.x % TAN_NODES;
-  if (P >= np1 * np1 * np1) return;
-  const int s = tan_slot_order[threadIdx.x / TAN_NODES];
-  const int di = s % 3 - 1, dj = (s / 3) % 3 - 1, dk = s / 9 - 1;
-  const int i = (int)(P % np1), j = (int)((P / np1) % np1), k = (int)(P / (np1 * np1));
-  const int qi = i + di, qj = j + dj, qk = k + dk;
-  if (qi < 0 || qi > n || qj < 0 || qj > n || qk < 0 || qk > n) return;
-  const T inv_h = T(1.0 / a.h), w = T(0.125 * a.h * a.h * a.h);
-  T B[3][3] = {};
-  const int ea0 = max(max(i, qi) - 1, 0), ea1 = min(min(i, qi), n - 1);
-  const int eb0 = max(max(j, qj) - 1, 0), eb1 = min(min(j, qj), n - 1);
-  const int ec0 = max(max(k, qk) - 1, 0), ec1 = min(min(k, qk), n - 1);
-  for (int ec = ec0; ec <= ec1; ++ec)
-    for (int eb = eb0; eb <= eb1; ++eb)
-      for (int ea = ea0; ea <= ea1; ++ea) {
-        const int64_t e = ea + (int64_t)n * (eb + (int64_t)n * ec);
-        for (int qp = 0; qp < 8; ++qp) {
-          const int p = qp & 1, q = (qp >> 1) & 1, r = qp >> 2;
-          QpTangent<T> tq;
-          load_qp_tangent<T, MS>(a, e, qp, tq);
-          T gP[3], gQ[3];
-          basis_grad(i - ea, j - eb, k - ec, p, q, r, inv_h, gP);
-          basis_grad(qi - ea, qj - eb, qk - ec, p, q, r, inv_h, gQ);
-          block_add(tq, gP, gQ, w, B);
-        }
-      }
-  const int cx = axis_cnt(i, n), cy = axis_cnt(j, n), cz = axis_cnt(k, n);
-  const int len = 3 * cx * cy * cz;
-  const int rank = axis_rank(k, dk) * cx * cy + axis_rank(j, dj) * cx + axis_rank(i, di);
-  const int64_t start = node_row_start(i, j, k, n);
-  const int64_t Q = qi + np1 * (qj + np1 * qk);
-  for (int c = 0; c < 3; ++c) {
-    const int64_t base = start + (int64_t)c * len + 3 * rank;
-    const bool rc = apply_bc && a.mask && a.mask[3 * P + c];
-    for (int d = 0; d < 3; ++d) {
-      T v = B[c][d];
-      if (apply_bc && a.mask && (rc || a.mask[3 * Q + d])) v = (P == Q && c == d) ? T(1) : T(0);
-      vals[base + d] = v;
-    }
-  }
-}
-
-// CSR values, small-strain models (linear, J2 and the surrogate's Voigt tangents): a workgroup
-// takes TR_NODES consecutive nodes of one x-row of nodes, whose CSR rows are one contiguous
-// segment.  Phase 1 forms the Gauss-point coefficients (lp, mp, beta, N) of the elements
-// around the tile once into LDS.  Phase 2: lane (node, task), one wave per node; the 64 tasks
+// CSR values (linear, J2 with the surrogate's Voigt tangents, Neo-Hookean): a workgroup takes
+// TR_NODES consecutive nodes of one x-row of nodes, whose CSR rows are one contiguous segment.
+// Phase 1 forms the Gauss-point coefficients of the elements around the tile once into LDS
+// ((lp, mp, beta, N) of the small-strain laws; lam, mu, F^-T, ln J at Neo-Hookean points).  Phase 2: lane (node, task), one wave per node; the 64 tasks
 // of a node are the (neighbour, shared element) pairs: per axis the neighbour offset d and the
 // element offset o (element = node + o) take (d, o) = (-1, -1), (0, -1), (0, 0) or (1, 0), so
 // 4^3 tasks cover the 27 neighbours with their 1, 2, 4 or 8 shared elements; each lane sums
@@ -1160,7 +1099,10 @@ constexpr int TR_SETS = (TR_NODES + 1) * 2 * 2 * 8;  // (element, Gauss point) c
 
 template <typename T, int MS>
 __global__ __launch_bounds__(256) void tangent_rows_kernel(TanArgs a, T* vals, int apply_bc) {
-  __shared__ T s_co[9][TR_SETS];  // lp, mp, beta, N (xx yy zz yz xz xy); component-major
+  // per set, component-major: small-strain laws lp, mp, beta, N (xx yy zz yz xz xy); Neo-Hookean
+  // problems lam, mu, a flag (1: Neo-Hookean point, 0: linear phase), F^-T (row-major), ln J
+  constexpr int NCO = MS == MS_NH ? 13 : 9;
+  __shared__ T s_co[NCO][TR_SETS];
   __shared__ int s_sur[TR_SETS];  // surrogate points: slot of their Voigt tangent, else -1
   __shared__ T s_part[9][256];    // each task's 3x3 block, component-major (conflict-free)
   __shared__ uint8_t s_mk[3][3][TR_NODES + 2][3];  // constrained flags of the tile's nodes and neighbours
@@ -1176,8 +1118,9 @@ __global__ __launch_bounds__(256) void tangent_rows_kernel(TanArgs a, T* vals, i
 
   // phase 1: elements (i0 - 1 .. i0 + TR_NODES - 1) x (j - 1, j) x (k - 1, k), all 8 points.
   // Every load of the phase is issued before any of them is used: the constrained-dof flags of
-  // the tile's nodes, and per set the phase id, modulus scale and the six stored-tangent words
-  // (read for every element: the words exist for all of them and are used at J2 points only)
+  // the tile's nodes, and per set the phase id, modulus scale and the stored-tangent words (six
+  // for J2, ten for Neo-Hookean problems; read for every element: the words exist for all of
+  // them and are used at points of that law only)
   static_assert(TR_SETS <= 256, "one coefficient set per lane");
   uint8_t mk_v = 0;
   const bool mk_lane = tid < 27 * (TR_NODES + 2);
@@ -1196,21 +1139,29 @@ __global__ __launch_bounds__(256) void tangent_rows_kernel(TanArgs a, T* vals, i
     const int qp = si & 7, el = si >> 3;
     const int xl = el % (TR_NODES + 1), yl = (el / (TR_NODES + 1)) & 1, zl = el / (2 * (TR_NODES + 1));
     const int ea = i0 - 1 + xl, eb = j - 1 + yl, ec = k - 1 + zl;
-    T co[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    T co[NCO];
+#pragma unroll
+    for (int q = 0; q < NCO; ++q) co[q] = 0;
     int sur = -1;
     if (si < TR_SETS && ea >= 0 && ea < n && eb >= 0 && eb < n && ec >= 0 && ec < n) {
       const int64_t e = ea + (int64_t)n * (eb + (int64_t)n * ec);
       const int ph = a.phase[e];
       const T sc = a.scale ? static_cast<const T*>(a.scale)[e] : T(1);
-      T tn[6];
-      if (MS == MS_J2) {
+      constexpr int NW = MS == MS_NH ? 10 : 6;
+      T tn[NW];
+      if (MS != MS_LINEAR) {
         const T* tg = static_cast<const T*>(a.tangent);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) tn[q] = tg[(int64_t)(q * 8 + qp) * ne + e];
+        for (int q = 0; q < NW; ++q) tn[q] = tg[(int64_t)(q * 8 + qp) * ne + e];
       }
       const PhaseConst pc = a.mat.ph[ph];
       co[0] = T(pc.lam) * sc;
       co[1] = T(pc.mu) * sc;
+      if (MS == MS_NH && pc.model == FE_NEOHOOKE) {
+        co[2] = 1;
+#pragma unroll
+        for (int q = 0; q < 10; ++q) co[3 + q] = tn[q];
+      }
       if (MS == MS_J2 && pc.model == FE_J2) {
         T N[6];
         if (tn[0] < T(-1.5)) {
@@ -1229,7 +1180,7 @@ __global__ __launch_bounds__(256) void tangent_rows_kernel(TanArgs a, T* vals, i
     const unsigned long long bal = __ballot(iso);
     if (si < TR_SETS) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) s_co[q][si] = co[q];
+      for (int q = 0; q < NCO; ++q) s_co[q][si] = co[q];
       s_sur[si] = sur;
       if ((si & 7) == 0) s_uni[si >> 3] = ((bal >> (tid & 63 & ~7)) & 0xffull) == 0xffull ? 1 : 0;
     }
@@ -1281,11 +1232,27 @@ __global__ __launch_bounds__(256) void tangent_rows_kernel(TanArgs a, T* vals, i
       T ga[3], gb[3];
       basis_grad(-ox, -oy, -oz, p, q, r, inv_h, ga);               // the row node's corner
       basis_grad(dx - ox, dy - oy, dz - oz, p, q, r, inv_h, gb);   // the neighbour's corner
-      T co[9];
+      T co[NCO];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) co[q] = s_co[q][sb + qp];
+      for (int q = 0; q < NCO; ++q) co[q] = s_co[q][sb + qp];
       const int sur = MS == MS_J2 ? s_sur[sb + qp] : -1;
-      if (sur >= 0) {
+      if (MS == MS_NH && co[2] != T(0)) {
+        // w (mu (ga.gb) I + (mu - lam ln J) (F^-T gb)(F^-T ga)^T + lam (F^-T ga)(F^-T gb)^T)
+        T va[3], vb[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          va[c] = co[3 + 3 * c] * ga[0] + co[4 + 3 * c] * ga[1] + co[5 + 3 * c] * ga[2];
+          vb[c] = co[3 + 3 * c] * gb[0] + co[4 + 3 * c] * gb[1] + co[5 + 3 * c] * gb[2];
+        }
+        const T wm = w * co[1], wc = w * (co[1] - co[0] * co[12]), wl = w * co[0];
+        const T t = wm * (ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          B[c][c] += t;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) B[c][d] += wc * vb[c] * va[d] + wl * va[c] * vb[d];
+        }
+      } else if (sur >= 0) {
         QpTangent<T> t;
         t.kind = 2;
         t.D = static_cast<const float*>(a.sur_D) + (int64_t)sur * 36;
@@ -1364,36 +1331,21 @@ __global__ __launch_bounds__(256) void tangent_rows_kernel(TanArgs a, T* vals, i
 hipError_t launch_tangent_csr(const fe_problem* p, void* vals, int apply_bc, hipStream_t s) {
   if (p->general) return gen_tangent(p, vals, apply_bc, tan_args(p), s);
   const TanArgs a = tan_args(p);
-  if (p->model_set != MS_NH) {
-    const int64_t np1 = p->n + 1;
-    const dim3 rgrid((unsigned)(np1 * np1 * ((np1 + TR_NODES - 1) / TR_NODES))), rblock(256);
-    if (p->prec == FE_F64) {
-      if (p->model_set == MS_J2)
-        timed_launch((tangent_rows_kernel<double, MS_J2>), rgrid, rblock, 0, s, a, (double*)vals, apply_bc);
-      else
-        timed_launch((tangent_rows_kernel<double, MS_LINEAR>), rgrid, rblock, 0, s, a, (double*)vals, apply_bc);
-    } else {
-      if (p->model_set == MS_J2)
-        timed_launch((tangent_rows_kernel<float, MS_J2>), rgrid, rblock, 0, s, a, (float*)vals, apply_bc);
-      else
-        timed_launch((tangent_rows_kernel<float, MS_LINEAR>), rgrid, rblock, 0, s, a, (float*)vals, apply_bc);
-    }
-    return hipGetLastError();
-  }
-  const dim3 grid((unsigned)((p->n_nodes + TAN_NODES - 1) / TAN_NODES)), block(TAN_BLOCK);
+  const int64_t np1 = p->n + 1;
+  const dim3 grid((unsigned)(np1 * np1 * ((np1 + TR_NODES - 1) / TR_NODES))), block(256);
   if (p->prec == FE_F64) {
     double* v = (double*)vals;
     switch (p->model_set) {
-      case MS_J2: timed_launch((tangent_csr_kernel<double, MS_J2>), grid, block, 0, s, a, v, apply_bc); break;
-      case MS_NH: timed_launch((tangent_csr_kernel<double, MS_NH>), grid, block, 0, s, a, v, apply_bc); break;
-      default: timed_launch((tangent_csr_kernel<double, MS_LINEAR>), grid, block, 0, s, a, v, apply_bc);
+      case MS_J2: timed_launch((tangent_rows_kernel<double, MS_J2>), grid, block, 0, s, a, v, apply_bc); break;
+      case MS_NH: timed_launch((tangent_rows_kernel<double, MS_NH>), grid, block, 0, s, a, v, apply_bc); break;
+      default: timed_launch((tangent_rows_kernel<double, MS_LINEAR>), grid, block, 0, s, a, v, apply_bc);
     }
   } else {
     float* v = (float*)vals;
     switch (p->model_set) {
-      case MS_J2: timed_launch((tangent_csr_kernel<float, MS_J2>), grid, block, 0, s, a, v, apply_bc); break;
-      case MS_NH: timed_launch((tangent_csr_kernel<float, MS_NH>), grid, block, 0, s, a, v, apply_bc); break;
-      default: timed_launch((tangent_csr_kernel<float, MS_LINEAR>), grid, block, 0, s, a, v, apply_bc);
+      case MS_J2: timed_launch((tangent_rows_kernel<float, MS_J2>), grid, block, 0, s, a, v, apply_bc); break;
+      case MS_NH: timed_launch((tangent_rows_kernel<float, MS_NH>), grid, block, 0, s, a, v, apply_bc); break;
+      default: timed_launch((tangent_rows_kernel<float, MS_LINEAR>), grid, block, 0, s, a, v, apply_bc);
     }
   }
   return hipGetLastError();
