@@ -437,11 +437,20 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
   const int ph = valid ? (int)a.phase[e] : 0;
   const T* tang_c = static_cast<const T*>(a.tangent);
   T tq0[8];
+  T nw[2][10];  // Neo-Hookean operator: F^-T and ln J of two Gauss points (see below)
+  // (FP32 requests the first point's words with the staging, measured faster there; FP64 after
+  // the gradients, measured faster there)
+  constexpr bool NH_EARLY = sizeof(T) == 4;
   auto early = [&]() {
     if (APPLY_LIKE && MS == MS_J2) {
       const bool j2 = valid && a.mat.ph[ph].model == FE_J2;
 #pragma unroll
       for (int qq = 0; qq < 8; ++qq) tq0[qq] = j2 ? tang_c[(int64_t)qq * ne + e] : T(-1);
+    }
+    if (APPLY_LIKE && MS == MS_NH && NH_EARLY) {
+      const bool nh = valid && a.mat.ph[ph].model == FE_NEOHOOKE;
+#pragma unroll
+      for (int k = 0; k < 10; ++k) nw[0][k] = nh ? tang_c[(int64_t)(k * 8) * ne + e] : T(0);
     }
   };
 
@@ -521,13 +530,12 @@ __global__ __launch_bounds__(EBLOCK) __attribute__((amdgpu_waves_per_eu(2))) voi
 
     // Neo-Hookean operator: F^-T and ln J of the linearisation, stored by the residual per
     // Gauss point ([10][8][n_el]), requested one point ahead of their use
-    T nw[2][10];
     const bool nh_el = MS == MS_NH && pc.model == FE_NEOHOOKE;
     auto load_nh = [&](int qp, T* w) {
 #pragma unroll
       for (int k = 0; k < 10; ++k) w[k] = nh_el ? tang_c[(int64_t)(k * 8 + qp) * ne + e] : T(0);
     };
-    if (APPLY_LIKE && MS == MS_NH) load_nh(0, nw[0]);
+    if (APPLY_LIKE && MS == MS_NH && !NH_EARLY) load_nh(0, nw[0]);
 
     T Px[2][2][3], Py[2][2][3], Pz[2][2][3];
 #pragma unroll
