@@ -33,3 +33,27 @@ def test_nodal_spmv(n, prec):
     tol = 1e-13 if prec == "f64" else 1e-5
     assert rel_err(y2, y_ref) <= tol
     assert rel_err(y2, y1) <= tol
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_general_spmv_arbitrary_rows(prec):
+    """fe_apply_csr on a matrix that is not a mesh pattern: random row lengths 0..100 (empty rows,
+    single entries, lengths on both sides of the kernel's two-step batches), random columns,
+    against the oracle's CSR mat-vec."""
+    import torch
+    from paper_2604_22087_amd import fe
+    print(f"[general spmv arbitrary rows] {prec}", flush=True)
+    P = fe.Problem(5, prec)
+    rng = np.random.default_rng(7)
+    lens = rng.integers(0, 101, size=P.n_dof)
+    lens[:40] = np.arange(40)  # every short length, 0 .. 39, at least once
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = rng.integers(0, P.n_dof, size=int(rp[-1])).astype(np.int32)
+    v = rng.normal(size=int(rp[-1]))
+    x = rng.normal(size=P.n_dof)
+    y_ref = assembly.csr_matvec(rp, ci, v, x)
+    y = P.apply_csr(torch.tensor(rp, device="cuda"), torch.tensor(ci, device="cuda"),
+                    torch.tensor(v, dtype=P.dtype, device="cuda"), torch.tensor(x, dtype=P.dtype, device="cuda"))
+    y = y.double().cpu().numpy()
+    assert np.all(y[lens == 0] == 0)
+    assert rel_err(y, y_ref) <= (1e-13 if prec == "f64" else 1e-5)
