@@ -88,3 +88,42 @@ def test_nh_inverted_element_flag():
     P.residual(u)
     assert P.read_flags() & 1
     assert P.read_flags() == 0  # reading clears
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_nh_with_linear_phase(prec):
+    """A linear sphere inside a Neo-Hookean matrix (n = 9: node rows split into ragged tiles):
+    residual, CSR tangent (plain and with the constrained dofs eliminated), matrix-free operator
+    and diagonal against the oracle -- the tangent kernel's Neo-Hookean sets and its linear sets,
+    the latter summed in closed form, in one assembly."""
+    import torch
+    from paper_2604_22087_amd import fe
+    print(f"[nh + linear phase] prec={prec}", flush=True)
+    n = 9
+    spec = [("neohooke", 2.6, 0.3), ("linear", 70.0, 0.22)]
+    phase = inputs.sphere_phase(n)
+    rve = RVE(n, phase, oracle_phases(spec))
+    amp = 0.3 / n
+    u = (rve.coords @ np.array([[0.06, 0.01, 0.0], [0.0, -0.02, 0.01], [0.01, 0.0, 0.04]]).T).ravel() \
+        + inputs.random_displacement(n, -amp, amp, seed=4)
+    r_e, k_e, _ = rve.element_residual_tangent(u)
+    R = assembly.assemble_vector(rve.conn, r_e, rve.n_dof)
+    rp, ci, v = assembly.assemble_csr(rve.conn, k_e, rve.n_dof)
+    mask = inputs.boundary_dof_mask(n)
+    P = fe.Problem(n, prec)
+    models, params = lib_materials(spec)
+    P.set_materials(torch.tensor(phase, dtype=torch.uint8, device="cuda"), models, params)
+    P.set_dirichlet(torch.tensor(mask, device="cuda"))
+    tol = TOL[prec]
+    ut = torch.tensor(u, dtype=P.dtype, device="cuda")
+    assert rel_err(_np(P.residual(ut, store_tangent=True)), R) <= tol
+    assert rel_err(_np(P.tangent_csr(ut)), v) <= tol
+    # eliminated: rows and columns of constrained dofs zero, unit diagonal there
+    rows = assembly.csr_rows(rp)
+    fixed = (mask[rows] != 0) | (mask[ci] != 0)
+    v_bc = np.where(fixed, np.where(rows == ci, 1.0, 0.0), v)
+    assert rel_err(_np(P.tangent_csr(ut, apply_bc=True)), v_bc) <= tol
+    x = np.random.default_rng(5).normal(size=rve.n_dof)
+    xt = torch.tensor(x, dtype=P.dtype, device="cuda")
+    assert rel_err(_np(P.apply_matfree(xt)), assembly.csr_matvec(rp, ci, v, x)) <= tol
+    assert rel_err(_np(P.diagonal()), solver.matfree_diagonal(rve.conn, k_e, rve.n_dof)) <= tol
