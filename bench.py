@@ -514,7 +514,7 @@ def main():
     ap.add_argument("--copy-calib", action="store_true", help="run only a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the library runs on a single GPU; how the path would shard across GPUs is a design note)", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.copy_calib:

@@ -1,7 +1,7 @@
 """Pins of the oracle on general (distorted, renumbered) hex8 meshes.
 
 The isoparametric element (oracle/hex8.py) and the sorted COO assembly (oracle/assembly.py)
-are the definitions the general-mesh GPU path is judged against; on a distorted mesh with
+are the definitions the general-mesh GPU path is checked against; on a distorted mesh with
 random node and element numbering and randomly rotated local orders they must still
 satisfy what the mathematics fixes:
   * the generated mesh fills the unit cube: sum of w detJ = 1, every detJ > 0;
